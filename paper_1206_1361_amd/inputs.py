@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs and workload definitions.
+
+Shared by the tests, the benchmark and the smoke check; holds none of the
+step's arithmetic (no sub-step, no sweep, no observable).  Every state is
+numpy complex128 of shape (Nz, Ny, Nx) on the node grid x_i = (i-(N-1)/2) dx,
+normalised so that dx*dy*dz*sum|psi|^2 = 1 where the workload says
+"normalised".
+
+The paper's own input files are not available, so these stand in for them:
+the workloads below carry the grid sizes, traps, couplings and initial-state
+shapes of the target configurations (a Gaussian, a Thomas-Fermi profile with
+noise, a ground-state-like profile with phase noise).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+def axis(n: int, d: float) -> np.ndarray:
+    """Node coordinates of one axis, symmetric about 0."""
+    return (np.arange(n, dtype=np.float64) - 0.5 * (n - 1)) * d
+
+
+def mesh(grid, dx):
+    """Broadcastable (z, y, x) coordinate arrays for grid (Nx, Ny, Nz)."""
+    nx, ny, nz = grid
+    x = axis(nx, dx[0])[None, None, :]
+    y = axis(ny, dx[1])[None, :, None]
+    z = axis(nz, dx[2])[:, None, None]
+    return x, y, z
+
+
+def normalise(psi: np.ndarray, dx) -> np.ndarray:
+    """Scale psi (in place) to dx*dy*dz*sum|psi|^2 = 1: defines a normalised input."""
+    s = float(np.vdot(psi, psi).real) * dx[0] * dx[1] * dx[2]
+    psi *= 1.0 / math.sqrt(s)
+    return psi
+
+
+def gaussian(grid, dx, omega) -> np.ndarray:
+    """exp(-(gamma x^2 + nu y^2 + lambda z^2)/2), normalised."""
+    x, y, z = mesh(grid, dx)
+    g, n, l = omega
+    psi = np.exp(-0.5 * (g * x * x + n * y * y + l * z * z)).astype(np.complex128)
+    return normalise(psi, dx)
+
+
+def mu_thomas_fermi(omega, g: float) -> float:
+    """Thomas-Fermi chemical potential 1/2 (15 g gamma nu lambda / (4 pi))^(2/5)."""
+    return 0.5 * (15.0 * g * omega[0] * omega[1] * omega[2] / (4.0 * math.pi)) ** 0.4
+
+
+def thomas_fermi(grid, dx, omega, g: float, noise: float = 0.0, seed: int = 0,
+                 floor: float = 0.0) -> np.ndarray:
+    """sqrt(max(0, (mu_TF - V)/g)) + complex Gaussian noise of std `noise` per
+    component, normalised.  `floor` adds a small Gaussian tail so the state
+    has no exact zeros (optional)."""
+    x, y, z = mesh(grid, dx)
+    V = 0.5 * (omega[0] ** 2 * x * x + omega[1] ** 2 * y * y + omega[2] ** 2 * z * z)
+    mu = mu_thomas_fermi(omega, g)
+    psi = np.sqrt(np.maximum(0.0, (mu - V) / g)).astype(np.complex128)
+    if floor:
+        psi += floor * np.exp(-V / max(mu, 1e-300))
+    if noise:
+        rng = np.random.default_rng(seed)
+        shape = psi.shape
+        psi += noise * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    return normalise(psi, dx)
+
+
+def phase_noise(psi: np.ndarray, amplitude: float, seed: int) -> np.ndarray:
+    """psi * exp(i theta), theta ~ U(-amplitude, amplitude) per point (in place)."""
+    rng = np.random.default_rng(seed)
+    psi *= np.exp(1j * rng.uniform(-amplitude, amplitude, psi.shape))
+    return psi
+
+
+def random_state(grid, dx, seed: int) -> np.ndarray:
+    """Complex standard-normal values per point, normalised (parity inputs)."""
+    rng = np.random.default_rng(seed)
+    shape = (grid[2], grid[1], grid[0])
+    psi = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return normalise(psi, dx)
+
+
+def smooth_random_state(grid, dx, omega, seed: int) -> np.ndarray:
+    """A Gaussian envelope times a random complex field: smooth on the scale
+    of the trap but with every mode excited."""
+    psi = gaussian(grid, dx, omega) * (1.0 + 0.3 * random_state(grid, dx, seed) *
+                                       math.sqrt(dx[0] * dx[1] * dx[2] * grid[0] * grid[1] * grid[2]))
+    return normalise(psi, dx)
+
+
+def sine_mode(grid, modes) -> np.ndarray:
+    """prod_a sin(pi m_a (i_a + 1) / (N_a + 1)): unnormalised lattice sine mode."""
+    nx, ny, nz = grid
+    mx, my, mz = modes
+    sx = np.sin(math.pi * mx * (np.arange(nx) + 1) / (nx + 1))
+    sy = np.sin(math.pi * my * (np.arange(ny) + 1) / (ny + 1))
+    sz = np.sin(math.pi * mz * (np.arange(nz) + 1) / (nz + 1))
+    return (sz[:, None, None] * sy[None, :, None] * sx[None, None, :]).astype(np.complex128)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    grid: tuple          # (Nx, Ny, Nz)
+    dx: tuple
+    dt: float
+    omega: tuple         # (gamma, nu, lambda)
+    g: float
+    mode: str            # "imag" | "real"
+    steps: int
+    g_after: float | None = None   # real-time quench: g for the timed steps
+    description: str = ""
+
+    @property
+    def points(self) -> int:
+        return self.grid[0] * self.grid[1] * self.grid[2]
+
+
+# Smallest case: imaginary time, 32^3, dx 0.25, dt = 0.1 dx^2, trap (1, 1.4, 2),
+# g = 10, normalised Gaussian start, 200 steps.
+SMALL_IMAG = Workload(
+    name="imag-32^3", grid=(32, 32, 32), dx=(0.25,) * 3, dt=0.1 * 0.25 ** 2,
+    omega=(1.0, 1.4, 2.0), g=10.0, mode="imag", steps=200,
+    description="imaginary time, 32^3, dx 0.25, dt 0.1 dx^2, trap (1, 1.4, 2), g 10, Gaussian start")
+
+# Real-time quench: 240x200x160, dx 0.1, dt = 0.005 dx^2, trap (0.5, 1, 1.5),
+# ground state at g = 22 with 1e-3 phase noise, then g -> 11 for 1000 steps.
+QUENCH = Workload(
+    name="real-240x200x160-quench", grid=(240, 200, 160), dx=(0.1,) * 3, dt=0.005 * 0.1 ** 2,
+    omega=(0.5, 1.0, 1.5), g=22.0, g_after=11.0, mode="real", steps=1000,
+    description="real time, 240x200x160, dx 0.1, dt 5e-5, trap (0.5, 1, 1.5), g 22 -> 11")
+
+# Large real-time run: 512x512x384, dx 0.05, trap (1, 1.2, 4), g 2000,
+# Thomas-Fermi start with 1e-4 Gaussian noise, 500 steps; dt = 0.005 dx^2.
+LARGE_REAL = Workload(
+    name="real-512x512x384", grid=(512, 512, 384), dx=(0.05,) * 3, dt=0.005 * 0.05 ** 2,
+    omega=(1.0, 1.2, 4.0), g=2000.0, mode="real", steps=500,
+    description="real time, 512x512x384, dx 0.05, dt 1.25e-5, trap (1, 1.2, 4), g 2000, TF + 1e-4 noise")
+
+WORKLOADS = {w.name: w for w in (SMALL_IMAG, QUENCH, LARGE_REAL)}
+
+
+def initial_state(w: Workload, seed: int | None = None) -> np.ndarray:
+    """The documented starting state of a workload (host, complex128).
+
+    The quench workload starts from its imaginary-time ground state; that
+    state is produced by the method itself, so here it is stood in for by
+    the Thomas-Fermi profile of the same trap and g (with a small Gaussian
+    tail) times the 1e-3 phase noise.  The benchmark relaxes it in imaginary
+    time on the GPU before timing."""
+    if w is SMALL_IMAG or w.name == SMALL_IMAG.name:
+        return gaussian(w.grid, w.dx, w.omega)
+    if w.name == QUENCH.name:
+        psi = thomas_fermi(w.grid, w.dx, w.omega, w.g, floor=1e-3)
+        return phase_noise(psi, 1e-3, 2 if seed is None else seed)
+    if w.name == LARGE_REAL.name:
+        return thomas_fermi(w.grid, w.dx, w.omega, w.g, noise=1e-4, seed=5 if seed is None else seed)
+    raise KeyError(w.name)
