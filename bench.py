@@ -1,0 +1,226 @@
+"""Throughput of the split-step Crank-Nicolson step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: real-time propagation on a 512x512x384 grid (dx 0.05, dt 1.25e-5,
+trap (1, 1.2, 4), g 2000) from a seeded Thomas-Fermi profile with 1e-4
+Gaussian noise -- the single-GPU case whose footprint (1.5 GiB complex128,
+768 MiB complex64) exceeds the 256 MB Infinity Cache, so the step streams
+from HBM.  One step = calcnu + calclux, calcluy, calcluz over the whole grid.
+
+Prints one JSON line.  `value` is complex128 (FP64) grid-point steps per
+second over K timed steps with psi resident in HBM; the `fp32` object holds
+the complex64 run.  `roofline` is the dominant kernel's algorithmic bytes
+(one read + one write of psi per launch) over its mean duration from HIP
+events recorded on the plan's stream inside the timed region, against the
+8 TB/s HBM3E peak.  `cpu_baseline` is the FP64 oracle timed on this host's
+cores over a bounded sample of the same workload.  `latency` is the
+end-to-end time of the small imaginary-time solve (32^3, 200 steps),
+upload to observables on the host, p50/p99 over repeated solves.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import pathlib
+import sys
+import time
+
+import numpy as np
+
+ROOT = pathlib.Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "grid-point SSCN steps/sec (FP64 vs FP32) as % HBM roofline; p50/p99 solve latency"
+UNIT = "grid-point-steps/s"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = {
+    "nu_x": "paper_1206_1361_amd/csrc/sweep_x.hip",
+    "y": "paper_1206_1361_amd/csrc/sweep_yz.hip",
+    "z": "paper_1206_1361_amd/csrc/sweep_yz.hip",
+}
+TRAFFIC_FILE = ROOT / "profiles" / "pmc_traffic.json"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_digest(path: str) -> str:
+    return hashlib.sha256((ROOT / path).read_bytes()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, dtype: str):
+    """HBM bytes per launch from the committed PMC summary, or None if the
+    kernel's source has changed since the counters were taken."""
+    try:
+        rec = json.loads(TRAFFIC_FILE.read_text())["kernels"][f"{kernel}/{dtype}"]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_dtype(gp, torch, w, psi_host, dtype: str, steps: int, warmup: int) -> dict:
+    psi = torch.from_numpy(psi_host).to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+    bpp = 16 if dtype == "c128" else 8
+    points = w.points
+    with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype=dtype) as plan:
+        log(f"[bench] {dtype}: {plan.describe()}")
+        n0 = plan.observables(psi)["norm"]
+        plan.step(psi, warmup)
+        plan.sync()
+        plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(psi, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = plan.profile_read()
+        plan.profile(False)
+        n1 = plan.observables(psi)["norm"]
+    elapsed = t1 - t0
+    kernels = {}
+    for name, (ms, count) in prof.items():
+        if count:
+            avg = ms / count
+            alg = 2 * points * bpp   # one read and one write of psi per launch
+            kernels[name] = {"launches": count, "avg_ms": avg,
+                             "alg_bytes": alg, "gbs": alg / (avg * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    d = kernels[dom]
+    traffic = measured_traffic(dom, dtype)
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic}
+    step_bytes = 3 * 2 * points * bpp
+    return {
+        "value": points * steps / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "roofline": roof,
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "GB/s": round(v["gbs"], 1),
+                        "frac": round(v["gbs"] / HBM_PEAK_GBS, 4)} for k, v in kernels.items()},
+        "step_hbm_frac": round(step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "norm_drift": abs(n1 - n0),
+    }
+
+
+def cpu_baseline(w, psi_host, budget_s: float) -> dict:
+    import oracle
+
+    cores = oracle.get_threads()
+    psi = psi_host.copy()
+    mode = oracle.REAL if w.mode == "real" else oracle.IMAG
+    t0 = time.perf_counter()
+    oracle.step(psi, w.dx, w.dt, w.omega, w.g, mode, 1)
+    one = time.perf_counter() - t0
+    more = max(0, min(int(budget_s / max(one, 1e-9)) - 1, w.steps - 1))
+    t1 = time.perf_counter()
+    if more:
+        oracle.step(psi, w.dx, w.dt, w.omega, w.g, mode, more)
+    total = one + (time.perf_counter() - t1)
+    n = 1 + more
+    return {"value": w.points * n / total, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"{n} of the {w.steps} real-time steps of the {w.name} grid, complex128, "
+                      f"{total:.1f} s on {cores} threads"}
+
+
+def latency(gp, torch, repeats: int) -> dict:
+    from paper_1206_1361_amd import inputs
+
+    w = inputs.SMALL_IMAG
+    psi0 = inputs.initial_state(w)
+    times = []
+    with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype="c128") as plan:
+        for r in range(repeats + 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi = torch.from_numpy(psi0).cuda()
+            plan.step(psi, w.steps)
+            plan.observables(psi)
+            t1 = time.perf_counter()
+            if r >= 2:
+                times.append((t1 - t0) * 1e3)
+    return {"workload": w.name, "steps": w.steps, "dtype": "c128", "solves": len(times),
+            "p50_ms": round(float(np.percentile(times, 50)), 3),
+            "p99_ms": round(float(np.percentile(times, 99)), 3)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp32", default="c64", choices=["c64", "c64_f64"],
+                    help="complex64 variant reported in the fp32 object")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--latency-repeats", type=int, default=50)
+    ap.add_argument("--only", choices=["c128", "c64", "c64_f64"], default=None,
+                    help="run one dtype only (profiling runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the step is measured on a single MI355X "
+              "(multi-GPU sharding of one grid is a design, not part of this build).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1206_1361_amd as gp
+    from paper_1206_1361_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    gp.lib()
+    w = inputs.LARGE_REAL
+    log(f"[bench] generating the {w.name} initial state")
+    psi_host = inputs.initial_state(w)
+
+    dtypes = [args.only] if args.only else ["c128", args.fp32]
+    res = {}
+    for dt in dtypes:
+        log(f"[bench] timing {dt}: {args.warmup} warmup + {args.steps} steps")
+        res[dt] = run_dtype(gp, torch, w, psi_host, dt, args.steps, args.warmup)
+        log(f"[bench] {dt}: {res[dt]['ms_per_step']:.3f} ms/step, {res[dt]['kernels']}")
+
+    primary = "c128" if "c128" in res else dtypes[0]
+    p = res[primary]
+    out = {
+        "metric": METRIC, "value": p["value"], "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": p["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if primary in ("c128", "c64_f64") else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.grid), "dx": w.dx[0], "dt": w.dt,
+                   "trap": list(w.omega), "g": w.g, "mode": w.mode,
+                   "storage": "complex128" if primary == "c128" else "complex64"},
+        "roofline": p["roofline"],
+        "kernels": p["kernels"],
+        "step_hbm_frac": p["step_hbm_frac"],
+        "norm_drift": p["norm_drift"],
+    }
+    for dt in dtypes:
+        if dt != primary:
+            q = res[dt]
+            out["fp32"] = {"storage": "complex64", "arithmetic": "f32" if dt == "c64" else "f64",
+                           "value": q["value"], "ms_per_step": q["ms_per_step"],
+                           "roofline": q["roofline"], "kernels": q["kernels"],
+                           "step_hbm_frac": q["step_hbm_frac"], "norm_drift": q["norm_drift"]}
+    if args.latency_repeats > 0:
+        log("[bench] latency of the small imaginary-time solve")
+        out["latency"] = latency(gp, torch, args.latency_repeats)
+    if not args.no_cpu_baseline:
+        log(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)")
+        out["cpu_baseline"] = cpu_baseline(w, psi_host, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

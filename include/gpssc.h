@@ -1,0 +1,206 @@
+/*
+ * gpssc.h -- C ABI of the MI355X (gfx950) split-step Crank-Nicolson step for
+ * the three-dimensional, fully anisotropic Gross-Pitaevskii equation.
+ *
+ * Method: Vudragovic, Vidanovic, Balaz, Muruganandam, Adhikari, "C programs
+ * for solving the time-dependent Gross-Pitaevskii equation in a fully
+ * anisotropic trap", Comput. Phys. Commun. 183 (2012) 2021.  Program
+ * summaries (v) imagtime3d and (xiv) realtime3d ("Method of solution"): the
+ * equation is discretised in space and time and propagated over small steps
+ * in imaginary time (stationary states) or real time (dynamics) by the
+ * split-step Crank-Nicolson method.  "Summary of revisions" names the parts
+ * of one step -- calcnu, calclux, calcluy, calcluz -- the normalisation
+ * calcnorm and the physical quantities calcmuen and calcrms; each entry point
+ * below says which of them it carries out.
+ *
+ * Conventions (the paper prints no formula; these readings fix them):
+ *   i dpsi/dt = [-1/2 Lap + V + g|psi|^2] psi,
+ *   V = 1/2 (gamma^2 x^2 + nu^2 y^2 + lambda^2 z^2);
+ *   nodes x_i = (i - (N-1)/2) dx on every axis, psi = 0 just outside the box;
+ *   psi is a device array of Nx*Ny*Nz complex numbers in C order (z, y, x):
+ *   element p = (k*Ny + j)*Nx + i, each complex stored as (re, im);
+ *   the norm is dx*dy*dz * sum |psi|^2.
+ *
+ * Error behaviour: every entry point returns a gp_status and never aborts or
+ * throws.  On GP_ERR_INVALID nothing is changed.  GP_ERR_DEVICE carries the
+ * HIP runtime message in gp_last_error().  Work queued by gp_step runs
+ * asynchronously; a failure it meets (a non-finite norm in imaginary time, a
+ * device fault) is reported by the next synchronous call (gp_observables,
+ * gp_sync).  A plan must not be used from two host threads at once; distinct
+ * plans are independent.
+ */
+#ifndef GPSSC_H
+#define GPSSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_plan gp_plan; /* opaque; created and owned by the library */
+
+/* Imaginary time converges to the ground state and renormalises every
+ * step; real time is the unitary dynamics. */
+typedef enum { GP_MODE_IMAG = 0, GP_MODE_REAL = 1 } gp_mode;
+
+/* GP_C128    : psi is complex<double> (16 B per point), FP64 arithmetic.
+ * GP_C64     : psi is complex<float>  (8 B per point), FP32 arithmetic in
+ *              the sweeps and the phase update.
+ * GP_C64_F64 : psi is complex<float>  (8 B per point), FP64 arithmetic in
+ *              registers (only the stored values are rounded to FP32).
+ * Every reduction (norm, energy, chemical potential, rms sizes) is
+ * accumulated in FP64 for all three. */
+typedef enum { GP_C128 = 0, GP_C64 = 1, GP_C64_F64 = 2 } gp_dtype;
+
+typedef enum {
+    GP_OK = 0,
+    GP_ERR_INVALID = 1,     /* bad argument: NULL, size mismatch, non-finite parameter */
+    GP_ERR_NOMEM = 2,       /* a device allocation failed */
+    GP_ERR_DEVICE = 3,      /* HIP runtime error; see gp_last_error() */
+    GP_ERR_NONFINITE = 4,   /* the norm or an observable is not finite (or the norm is 0) */
+    GP_ERR_UNSUPPORTED = 5  /* valid but outside what the kernels handle (line too long) */
+} gp_status;
+
+/* Physical quantities of psi (calcmuen, calcrms), all in FP64.  With
+ * N = dV sum|psi|^2 and psi-hat = psi / sqrt(N):
+ *   kinetic     = 1/2 dV sum_axes sum_links |psi_{i+1}-psi_i|^2 / dx_a^2 / N
+ *                 (3-point links, including the link to the zero outside
+ *                 the box at both ends of every line),
+ *   potential   = dV sum V |psi|^2 / N,
+ *   interaction = g dV sum |psi|^4 / N^2,
+ *   energy      = kinetic + potential + interaction / 2,
+ *   mu          = kinetic + potential + interaction,
+ *   rms[a]      = sqrt(dV sum a^2 |psi|^2 / N) about the origin,
+ *   rms_r       = sqrt(rms[0]^2 + rms[1]^2 + rms[2]^2),
+ *   mean[a]     = dV sum a |psi|^2 / N. */
+typedef struct {
+    double norm, mu, energy;
+    double rms[3], rms_r, mean[3];
+    double kinetic, potential, interaction;
+    int64_t steps_done; /* steps queued on this plan since creation */
+} gp_obs;
+
+/* Kernel classes reported by gp_profile_read. */
+enum {
+    GP_KERNEL_NU_X = 0,     /* calcnu + calclux (+ pending renormalisation) */
+    GP_KERNEL_Y = 1,        /* calcluy */
+    GP_KERNEL_Z = 2,        /* calcluz (+ per-block norm partial sums in imaginary time) */
+    GP_KERNEL_NORM = 3,     /* calcnorm: partial sums -> 1/sqrt(N) on the device */
+    GP_KERNEL_SCALE = 4,    /* end-of-call psi <- psi / sqrt(N) */
+    GP_KERNEL_OBS = 5,      /* calcmuen + calcrms sums and their finalisation */
+    GP_KERNEL_COUNT = 6
+};
+
+/* Creates a plan for one grid, step size, trap, coupling, mode and dtype.
+ *   grid[3]   Nx, Ny, Nz >= 1 (each <= 1024)
+ *   dx[3]     grid spacings > 0
+ *   dt        time step > 0 (imaginary or real time per `mode`)
+ *   gamma, nu, lambda  trap frequencies >= 0 along x, y, z
+ *   g         nonlinearity, any finite value
+ *   hip_stream  hipStream_t to queue work on, or NULL for the null stream
+ *   out       receives the plan
+ * Builds the constant Crank-Nicolson / Thomas coefficient tables of every
+ * axis on the host in FP64 (they depend on N, dx and dt, not on g) and copies
+ * them to the current device with the plan's scratch (reduction partials,
+ * the 1/sqrt(N) slot, an error flag).  Arguments are checked before any
+ * device call.  Returns GP_ERR_INVALID, GP_ERR_UNSUPPORTED, GP_ERR_NOMEM or
+ * GP_ERR_DEVICE on failure, with *out set to NULL. */
+gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt,
+                         double gamma, double nu, double lambda, double g,
+                         gp_mode mode, gp_dtype dtype, void *hip_stream,
+                         gp_plan **out);
+
+/* Frees the plan's tables and scratch after waiting for its stream.
+ * NULL-safe. */
+gp_status gp_plan_destroy(gp_plan *plan);
+
+/* Changes g (a quench) for the steps queued after this call.  The tables do
+ * not depend on g, so nothing is rebuilt. */
+gp_status gp_set_g(gp_plan *plan, double g);
+
+/* Changes the stream later work is queued on (hipStream_t or NULL). */
+gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
+
+/* Queues `nsteps` split-step Crank-Nicolson steps on psi, in place, and
+ * returns without waiting.  psi_dev is a device pointer to psi_elems complex
+ * numbers of the plan's dtype (psi_elems must equal Nx*Ny*Nz; 16-byte
+ * alignment for GP_C128, 8-byte for the complex64 dtypes); the caller owns it, and the
+ * library keeps no reference after the work completes.  One step is, in
+ * order: calcnu (psi <- exp(-tau (V + g|psi|^2)) psi, tau = dt or i dt),
+ * calclux, calcluy, calcluz (one Crank-Nicolson solve per grid line along
+ * each axis by the precomputed Thomas recursion) and, in imaginary time,
+ * calcnorm.  In imaginary time psi has norm 1 when the queued work ends; the
+ * per-step renormalisation is carried by the next step's first pass and a
+ * final scaling pass, which equals renormalising after every step up to
+ * rounding.  nsteps == 0 queues nothing.  The plan allocates nothing here. */
+gp_status gp_step(gp_plan *plan, void *psi_dev, int64_t psi_elems, int64_t nsteps);
+
+/* Waits for the plan's stream and reports a failure met by queued work:
+ * GP_ERR_NONFINITE after a non-finite or zero norm in imaginary time,
+ * GP_ERR_DEVICE after a runtime error.  Clears the recorded failure. */
+gp_status gp_sync(gp_plan *plan);
+
+/* Computes the physical quantities of psi (calcmuen, calcrms) and waits for
+ * them: one read pass over psi, FP64 partial sums per block, a fixed-order
+ * final sum (the result is bitwise reproducible), about 100 bytes copied to
+ * the host.  psi is not modified.  Returns GP_ERR_NONFINITE if the norm is
+ * zero or any quantity is not finite (out is still filled), and first
+ * reports any failure of earlier queued work as gp_sync does. */
+gp_status gp_observables(gp_plan *plan, const void *psi_dev, int64_t psi_elems,
+                         gp_obs *out);
+
+/* Device bytes a plan for this grid and dtype allocates (tables and
+ * scratch), excluding psi.  Returns 0 for an invalid grid. */
+size_t gp_plan_footprint_bytes(const int64_t grid[3], gp_dtype dtype);
+
+/* Writes a one-line description of the plan's launch shapes into buf
+ * (NUL-terminated, truncated to len). */
+gp_status gp_plan_describe(const gp_plan *plan, char *buf, size_t len);
+
+/* Static text for a status code. */
+const char *gp_status_string(gp_status s);
+
+/* Message of the last failure on the calling host thread ("" if none). */
+const char *gp_last_error(void);
+
+/* Per-kernel timing with HIP events on the plan's stream.  While enabled,
+ * every launch is bracketed by two events; gp_profile_read waits for the
+ * stream, adds the elapsed time of every bracketed launch per kernel class
+ * (GP_KERNEL_*) into ms[GP_KERNEL_COUNT], the launch counts into
+ * launches[GP_KERNEL_COUNT], and clears the record.  Disabled by default. */
+gp_status gp_profile_enable(gp_plan *plan, int on);
+gp_status gp_profile_read(gp_plan *plan, double *ms, int64_t *launches);
+
+/* Chunking the kernels use for a line of n points along `axis` (0 = x,
+ * 1 = y, 2 = z): `chunk` contiguous points per lane, `lanes` chunks per line
+ * (64 for x).  Host only.  GP_ERR_UNSUPPORTED if the line is too long. */
+gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *lanes);
+
+/* Host-only view of the constant sweep coefficients of one axis (no device
+ * call), for inspection and tests.  For a line of n points, spacing dx,
+ * step dt, mode and a chunking with chunk * lanes >= n, lanes <= 64, fills
+ * (every complex value as an (re, im) pair of doubles):
+ *   m[2*chunk*lanes]    Thomas pivots m_0 = 1/b, m_i = 1/(b - o^2 m_{i-1}),
+ *                       zero past the end of the line, position-major;
+ *   chunkprod[2*lanes]  product of a_i = -o m_i over each chunk;
+ *   scan[2*2*6*lanes]   Kogge-Stone multipliers [direction][stage][lane]:
+ *                       forward stage s, lane q = product of chunkprod over
+ *                       q-2^s+1 .. q (0 if q < 2^s); backward = product over
+ *                       q .. q+2^s-1 (0 if q+2^s >= lanes);
+ *   coef[8]             b = 1 + kappa, o = -kappa/2 (left operator),
+ *                       1 - kappa, kappa/2 (right operator), with
+ *                       kappa = tau / (2 dx^2), tau = dt or i dt.
+ * Lengths are counts of doubles.  GP_ERR_INVALID for bad arguments or short
+ * buffers. */
+gp_status gp_sweep_tables(int64_t n, double dx, double dt, gp_mode mode, int chunk,
+                          int lanes, double *m, size_t m_len, double *chunkprod,
+                          size_t chunkprod_len, double *scan, size_t scan_len,
+                          double *coef, size_t coef_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPSSC_H */

@@ -1,0 +1,293 @@
+"""ctypes binding over libgpssc.so (include/gpssc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libgpssc.  PyTorch supplies device memory (psi tensors) and the
+stream work is queued on.  If the library is missing, every entry point
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+PKG = pathlib.Path(__file__).resolve().parent
+LIBRARY = PKG / "libgpssc.so"
+
+IMAG = 0
+REAL = 1
+C128 = 0
+C64 = 1
+C64_F64 = 2
+
+OK = 0
+ERR_INVALID = 1
+ERR_NOMEM = 2
+ERR_DEVICE = 3
+ERR_NONFINITE = 4
+ERR_UNSUPPORTED = 5
+
+KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
+
+# Every symbol include/gpssc.h declares.
+EXPORTS = (
+    "gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_stream", "gp_step", "gp_sync",
+    "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
+    "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
+)
+
+
+class GPError(RuntimeError):
+    """A libgpssc call returned a status other than GP_OK."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class GPInvalid(GPError, ValueError):
+    pass
+
+
+class GPNoMemory(GPError, MemoryError):
+    pass
+
+
+class GPNonFinite(GPError, FloatingPointError):
+    pass
+
+
+class GPObs(ctypes.Structure):
+    _fields_ = [
+        ("norm", ctypes.c_double), ("mu", ctypes.c_double), ("energy", ctypes.c_double),
+        ("rms", ctypes.c_double * 3), ("rms_r", ctypes.c_double), ("mean", ctypes.c_double * 3),
+        ("kinetic", ctypes.c_double), ("potential", ctypes.c_double),
+        ("interaction", ctypes.c_double), ("steps_done", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "norm": self.norm, "mu": self.mu, "energy": self.energy,
+            "rms_x": self.rms[0], "rms_y": self.rms[1], "rms_z": self.rms[2], "rms_r": self.rms_r,
+            "mean_x": self.mean[0], "mean_y": self.mean[1], "mean_z": self.mean[2],
+            "kinetic": self.kinetic, "potential": self.potential,
+            "interaction": self.interaction, "steps_done": self.steps_done,
+        }
+
+
+_lib = None
+
+
+def library_path() -> pathlib.Path:
+    return LIBRARY
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgpssc.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIBRARY.exists():
+        raise ImportError(
+            f"{LIBRARY} is missing: build it with `python -m paper_1206_1361_amd.build` "
+            "(there is no CPU fallback)")
+    L = ctypes.CDLL(str(LIBRARY))
+    vp, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.gp_plan_create.argtypes = [i64p, dp, dbl, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int, vp,
+                                 ctypes.POINTER(vp)]
+    L.gp_plan_destroy.argtypes = [vp]
+    L.gp_set_g.argtypes = [vp, dbl]
+    L.gp_set_stream.argtypes = [vp, vp]
+    L.gp_step.argtypes = [vp, vp, i64, i64]
+    L.gp_sync.argtypes = [vp]
+    L.gp_observables.argtypes = [vp, vp, i64, ctypes.POINTER(GPObs)]
+    L.gp_plan_footprint_bytes.argtypes = [i64p, ctypes.c_int]
+    L.gp_plan_footprint_bytes.restype = sz
+    L.gp_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.gp_status_string.argtypes = [ctypes.c_int]
+    L.gp_status_string.restype = ctypes.c_char_p
+    L.gp_last_error.argtypes = []
+    L.gp_last_error.restype = ctypes.c_char_p
+    L.gp_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.gp_profile_read.argtypes = [vp, dp, i64p]
+    L.gp_sweep_shape.argtypes = [i64, ctypes.c_int, ctypes.c_int, ip, ip]
+    L.gp_sweep_tables.argtypes = [i64, dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  dp, sz, dp, sz, dp, sz, dp, sz]
+    for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_stream", "gp_step",
+                 "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
+                 "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str) -> None:
+    if status == OK:
+        return
+    L = lib()
+    msg = f"{what}: {L.gp_status_string(status).decode()} ({L.gp_last_error().decode()})"
+    cls = {ERR_INVALID: GPInvalid, ERR_NOMEM: GPNoMemory, ERR_NONFINITE: GPNonFinite}.get(status, GPError)
+    raise cls(status, msg)
+
+
+def _mode(mode) -> int:
+    if mode in (IMAG, "imag", "imaginary"):
+        return IMAG
+    if mode in (REAL, "real"):
+        return REAL
+    raise ValueError(f"unknown mode {mode!r}")
+
+
+def _dtype(dtype) -> int:
+    import torch
+
+    if dtype in (C128, "c128", "complex128", torch.complex128):
+        return C128
+    if dtype in (C64, "c64", "complex64", torch.complex64):
+        return C64
+    if dtype in (C64_F64, "c64_f64"):
+        return C64_F64
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def footprint_bytes(grid, dtype="c128") -> int:
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    return int(lib().gp_plan_footprint_bytes(g, _dtype(dtype)))
+
+
+def sweep_shape(n: int, axis: int, dtype="c128") -> tuple[int, int]:
+    c, l = ctypes.c_int(), ctypes.c_int()
+    _check(lib().gp_sweep_shape(int(n), int(axis), _dtype(dtype), ctypes.byref(c), ctypes.byref(l)),
+           "gp_sweep_shape")
+    return c.value, l.value
+
+
+def sweep_tables(n: int, dx: float, dt: float, mode, chunk: int, lanes: int) -> dict:
+    """Host-only copy of the sweep coefficients (see gp_sweep_tables)."""
+    import numpy as np
+
+    npad = chunk * lanes
+    m = np.zeros(2 * npad)
+    cp = np.zeros(2 * lanes)
+    sc = np.zeros(2 * 2 * 6 * lanes)
+    coef = np.zeros(8)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().gp_sweep_tables(int(n), float(dx), float(dt), _mode(mode), int(chunk), int(lanes),
+                                 m.ctypes.data_as(dp), m.size, cp.ctypes.data_as(dp), cp.size,
+                                 sc.ctypes.data_as(dp), sc.size, coef.ctypes.data_as(dp), coef.size),
+           "gp_sweep_tables")
+    c = lambda a: a[0::2] + 1j * a[1::2]  # noqa: E731
+    coefc = c(coef)
+    return {"m": c(m), "chunkprod": c(cp), "scan": c(sc).reshape(2, 6, lanes),
+            "b": coefc[0], "o": coefc[1], "rdiag": coefc[2], "roff": coefc[3]}
+
+
+class Plan:
+    """One grid, step size, trap, coupling, mode and dtype.
+
+    psi tensors are torch.complex128 (dtype "c128") or torch.complex64
+    ("c64": FP32 arithmetic, "c64_f64": FP64 arithmetic on FP32 storage),
+    CUDA (HIP) device, contiguous, shape (Nz, Ny, Nx).
+    """
+
+    def __init__(self, grid, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", stream=None):
+        import torch
+
+        L = lib()
+        self.grid = tuple(int(v) for v in grid)
+        self.dx = tuple(float(v) for v in (dx if hasattr(dx, "__len__") else (dx, dx, dx)))
+        self.dt = float(dt)
+        self.omega = (float(gamma), float(nu), float(lam))
+        self.g = float(g)
+        self.mode = _mode(mode)
+        self.dtype = _dtype(dtype)
+        self.torch_dtype = torch.complex128 if self.dtype == C128 else torch.complex64
+        self._handle = ctypes.c_void_p()
+        n = (ctypes.c_int64 * 3)(*self.grid)
+        d = (ctypes.c_double * 3)(*self.dx)
+        _check(L.gp_plan_create(n, d, self.dt, *self.omega, self.g, self.mode, self.dtype,
+                                self._stream_handle(stream), ctypes.byref(self._handle)),
+               "gp_plan_create")
+
+    @staticmethod
+    def _stream_handle(stream):
+        import torch
+
+        if stream is None:
+            if not torch.cuda.is_available():
+                return None
+            stream = torch.cuda.current_stream()
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def _psi(self, psi):
+        import torch
+
+        if not isinstance(psi, torch.Tensor):
+            raise TypeError("psi must be a torch tensor")
+        if psi.dtype != self.torch_dtype:
+            raise TypeError(f"psi must be {self.torch_dtype}, got {psi.dtype}")
+        if psi.device.type != "cuda":
+            raise ValueError("psi must live on the GPU")
+        if tuple(psi.shape) != self.grid[::-1]:
+            raise ValueError(f"psi must have shape (Nz, Ny, Nx) = {self.grid[::-1]}, got {tuple(psi.shape)}")
+        if not psi.is_contiguous():
+            raise ValueError("psi must be contiguous")
+        return ctypes.c_void_p(psi.data_ptr()), psi.numel()
+
+    def _use_current_stream(self):
+        _check(lib().gp_set_stream(self._handle, self._stream_handle(None)), "gp_set_stream")
+
+    def step(self, psi, nsteps: int = 1):
+        """Queue nsteps SSCN steps on psi (in place) on the current torch stream."""
+        ptr, n = self._psi(psi)
+        self._use_current_stream()
+        _check(lib().gp_step(self._handle, ptr, n, int(nsteps)), "gp_step")
+        return psi
+
+    def observables(self, psi) -> dict:
+        ptr, n = self._psi(psi)
+        self._use_current_stream()
+        out = GPObs()
+        _check(lib().gp_observables(self._handle, ptr, n, ctypes.byref(out)), "gp_observables")
+        return out.as_dict()
+
+    def sync(self) -> None:
+        _check(lib().gp_sync(self._handle), "gp_sync")
+
+    def set_g(self, g: float) -> None:
+        _check(lib().gp_set_g(self._handle, float(g)), "gp_set_g")
+        self.g = float(g)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().gp_plan_describe(self._handle, buf, len(buf)), "gp_plan_describe")
+        return buf.value.decode()
+
+    def profile(self, on: bool = True) -> None:
+        _check(lib().gp_profile_enable(self._handle, int(bool(on))), "gp_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel class: (total ms, launches)} since the last read."""
+        ms = (ctypes.c_double * len(KERNELS))()
+        cnt = (ctypes.c_int64 * len(KERNELS))()
+        _check(lib().gp_profile_read(self._handle, ms, cnt), "gp_profile_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) and self._handle.value:
+            lib().gp_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,141 @@
+// gp_internal.h -- types shared by the host plan and the gfx950 kernels of the
+// split-step Crank-Nicolson step.  Internal to libgpssc; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpssc {
+
+// Chunked Thomas layout limits.  A line of n points is cut into `lanes`
+// contiguous chunks of `chunk` points; the last chunks are padded with zeros.
+constexpr int kWave = 64;          // wavefront width on gfx950
+constexpr int kMaxChunkX = 16;     // x: 64 lanes x 16 points = 1024
+constexpr int kMaxLanesYZ = 64;    // y/z: at most 64 chunks per line
+constexpr int kMaxChunkYZ = 16;    // y/z: 64 x 16 = 1024 points per line
+constexpr int kMaxStages = 6;      // log2(64) Kogge-Stone stages
+constexpr int kMaxBlockYZ = 1024;  // threads per y/z block
+
+// Complex number in the arithmetic type A (double or float).
+template <typename A>
+struct cx {
+    A re, im;
+};
+
+template <typename A>
+__host__ __device__ __forceinline__ cx<A> mk(A re, A im) { return cx<A>{re, im}; }
+
+template <typename A>
+__device__ __forceinline__ cx<A> cadd(cx<A> a, cx<A> b) { return cx<A>{a.re + b.re, a.im + b.im}; }
+
+template <typename A>
+__device__ __forceinline__ cx<A> cmul(cx<A> a, cx<A> b)
+{
+    return cx<A>{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+
+// a*b + c
+template <typename A>
+__device__ __forceinline__ cx<A> cfma(cx<A> a, cx<A> b, cx<A> c)
+{
+    return cx<A>{fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im))};
+}
+
+template <typename A>
+__device__ __forceinline__ A cabs2(cx<A> a) { return fma(a.re, a.re, a.im * a.im); }
+
+// Storage <-> arithmetic conversion.  psi is stored as double2 (complex128)
+// or float2 (complex64).
+template <typename S> struct storage_traits;
+template <> struct storage_traits<double2> { using real = double; };
+template <> struct storage_traits<float2> { using real = float; };
+
+template <typename A, typename S>
+__device__ __forceinline__ cx<A> ld(S v) { return cx<A>{(A)v.x, (A)v.y}; }
+
+template <typename S, typename A>
+__device__ __forceinline__ S st(cx<A> v)
+{
+    using R = typename storage_traits<S>::real;
+    S r;
+    r.x = (R)v.re;
+    r.y = (R)v.im;
+    return r;
+}
+
+// Launch arguments of the calcnu + calclux kernel.
+template <typename A>
+struct XArgs {
+    int nx, ny, nz;
+    int nst_f, nst_b;    // Kogge-Stone stages whose multipliers are not all zero
+    A c0x, c0y, c0z;     // (N-1)/2 per axis: node i sits at (i - c0) * d
+    A dx, dy, dz;
+    A hgx, hgy, hgz;     // gamma^2/2, nu^2/2, lambda^2/2
+    A dt, g;
+    cx<A> o;             // off-diagonal of (1 + tau/2 T): -kappa/2
+    cx<A> rd, ro;        // (1 - tau/2 T): diagonal 1 - kappa, off-diagonal kappa/2
+};
+
+// Launch arguments of the strided (y or z) sweep kernel.
+template <typename A>
+struct SArgs {
+    int nx;                // columns across a block (x extent)
+    int n;                 // line length
+    int lanes;             // chunks per line (blockDim.y)
+    int nst_f, nst_b;
+    int64_t stride;        // element stride along the line
+    int64_t outer_stride;  // element stride per blockIdx.y
+    cx<A> o, rd, ro;
+};
+
+// Sums of the observables pass, FP64.
+enum {
+    OBS_DENS = 0, OBS_POT, OBS_QUART,
+    OBS_LINKX, OBS_LINKY, OBS_LINKZ,
+    OBS_M1X, OBS_M1Y, OBS_M1Z,
+    OBS_M2X, OBS_M2Y, OBS_M2Z,
+    OBS_NSUMS
+};
+
+template <typename A>
+struct ObsArgs {
+    int nx, ny, nz;
+    double c0x, c0y, c0z, dx, dy, dz;
+    double hgx, hgy, hgz;
+};
+
+// ---- host-side launchers (one translation unit per kernel family) ----
+
+// Precision of a launch: storage and arithmetic types (double2/double,
+// float2/float, float2/double).
+enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2 };
+
+// calcnu + calclux.  m: [chunk][64] Thomas pivots; scan: [2][kMaxStages][64]
+// stage multipliers (forward, backward).  scale: NULL or device double.
+
+hipError_t launch_nu_x(Prec prec, bool real, int chunk, void *psi, const void *args,
+                       const void *m, const void *scan, const double *scale,
+                       hipStream_t stream);
+
+// calcluy / calcluz.  m: [lanes*chunk] pivots; scan: [2][kMaxStages][lanes].
+// partials: NULL, or one double per block (sum |psi|^2 of the block's output).
+hipError_t launch_strided(Prec prec, int chunk, int xt, int nouter, void *psi,
+                          const void *args, const void *m, const void *scan,
+                          double *partials, hipStream_t stream);
+
+// calcnorm: sums `n` partials in a fixed order, writes 1/sqrt(dv*sum) to
+// *scale and raises *flag if the norm is not finite and positive.
+hipError_t launch_norm_finalize(const double *partials, int n, double dv, double *scale,
+                                int *flag, hipStream_t stream);
+
+// psi <- psi * (*scale)
+hipError_t launch_scale(bool c64, void *psi, int64_t elems, const double *scale,
+                        hipStream_t stream);
+
+// calcmuen + calcrms raw sums: partials [nblocks][OBS_NSUMS] then a fixed
+// order final sum into sums[OBS_NSUMS].
+int obs_num_blocks(int nx, int ny);
+hipError_t launch_observables(bool c64, const void *psi, const ObsArgs<double> &args,
+                              double *partials, double *sums, hipStream_t stream);
+
+}  // namespace gpssc

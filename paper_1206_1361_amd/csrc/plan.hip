@@ -1,0 +1,755 @@
+// plan.hip -- host side of libgpssc: argument checks, the constant
+// Crank-Nicolson / Thomas tables, device scratch, and the launch sequence of
+// one split-step Crank-Nicolson step.  Implements include/gpssc.h.
+//
+// Paper: "Method of solution" of program summaries (v) and (xiv) (split-step
+// Crank-Nicolson propagation in imaginary or real time over small steps) and
+// "Summary of revisions" (the routines calcnu, calclux, calcluy, calcluz,
+// calcnorm, calcmuen, calcrms that make up a step and its diagnostics).
+#include "gpssc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gp_internal.h"
+
+using gpssc::cx;
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gp_status fail(gp_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+gp_status fail_hip(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return GP_ERR_DEVICE;
+}
+
+const int kChunksX[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
+const int kChunksYZ[] = {1, 2, 4, 8, 16};
+
+// Chunking of a line of n points along `axis`: chunk points per lane, lanes
+// per line.  Returns false when the line is longer than the kernels handle.
+bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes)
+{
+    if (n < 1) return false;
+    if (axis == 0) {
+        for (int c : kChunksX)
+            if ((int64_t)c * gpssc::kWave >= n) {
+                *chunk = c;
+                *lanes = gpssc::kWave;
+                return true;
+            }
+        return false;
+    }
+    for (int c : kChunksYZ) {
+        const int64_t p = (n + c - 1) / c;
+        if (p <= gpssc::kMaxLanesYZ) {
+            *chunk = c;
+            *lanes = (int)p;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Columns per y/z block: as wide as 64 (one full wavefront of contiguous
+// x), narrowed so the block holds at most 1024 threads and not far wider
+// than the grid.
+int strided_columns(int64_t nx, int lanes)
+{
+    int xt = 64;
+    while (xt * lanes > gpssc::kMaxBlockYZ) xt /= 2;
+    while (xt > 16 && xt / 2 >= nx) xt /= 2;
+    return xt;
+}
+
+// Constant tables of one axis, FP64.
+struct AxisTables {
+    int64_t n = 0;
+    int chunk = 0, lanes = 0;
+    cplx b, o, rd, ro;               // left diagonal / off-diagonal, right diagonal / off-diagonal
+    std::vector<cplx> m;             // Thomas pivots, position-major, chunk*lanes, zero past n
+    std::vector<cplx> chunkprod;     // product of a_i = -o m_i over each chunk
+    std::vector<cplx> scan;          // [2][kMaxStages][lanes]: forward, backward stage multipliers
+};
+
+// Crank-Nicolson along one axis: (1 + tau/2 T) psi' = (1 - tau/2 T) psi with
+// T psi_i = -(psi_{i+1} - 2 psi_i + psi_{i-1})/(2 dx^2) and tau = dt or i dt.
+// With kappa = tau/(2 dx^2): left  b = 1 + kappa, o = -kappa/2;
+//                            right 1 - kappa and kappa/2.
+// Thomas pivots m_0 = 1/b, m_i = 1/(b - o c'_{i-1}), c'_i = o m_i.
+void build_axis(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t)
+{
+    const cplx tau = real ? cplx(0.0, dt) : cplx(dt, 0.0);
+    const cplx kappa = tau / (2.0 * dx * dx);
+    t.n = n;
+    t.chunk = chunk;
+    t.lanes = lanes;
+    t.b = 1.0 + kappa;
+    t.o = -0.5 * kappa;
+    t.rd = 1.0 - kappa;
+    t.ro = 0.5 * kappa;
+    const int64_t npad = (int64_t)chunk * lanes;
+    t.m.assign((size_t)npad, cplx(0.0, 0.0));
+    cplx cprev(0.0, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        t.m[(size_t)i] = 1.0 / (t.b - t.o * cprev);
+        cprev = t.o * t.m[(size_t)i];
+    }
+    t.chunkprod.assign((size_t)lanes, cplx(1.0, 0.0));
+    for (int q = 0; q < lanes; ++q)
+        for (int c = 0; c < chunk; ++c)
+            t.chunkprod[(size_t)q] *= -t.o * t.m[(size_t)q * chunk + c];
+    // Kogge-Stone multipliers.  Forward, stage s, lane q: product of the
+    // chunk products q-2^s+1 .. q (lane q adds lane q-2^s's partial).
+    // Backward: product of q .. q+2^s-1 (lane q adds lane q+2^s's partial).
+    t.scan.assign((size_t)2 * gpssc::kMaxStages * lanes, cplx(0.0, 0.0));
+    for (int s = 0; s < gpssc::kMaxStages; ++s) {
+        const int d = 1 << s;
+        for (int q = 0; q < lanes; ++q) {
+            if (q - d >= 0) {
+                cplx p(1.0, 0.0);
+                for (int l = q - d + 1; l <= q; ++l) p *= t.chunkprod[(size_t)l];
+                t.scan[(size_t)s * lanes + q] = p;
+            }
+            if (q + d <= lanes - 1) {
+                cplx p(1.0, 0.0);
+                for (int l = q; l <= q + d - 1; ++l) p *= t.chunkprod[(size_t)l];
+                t.scan[(size_t)(gpssc::kMaxStages + s) * lanes + q] = p;
+            }
+        }
+    }
+}
+
+// Stages with a nonzero multiplier once rounded to the arithmetic type;
+// every later stage is all zero too (its multipliers are products of the
+// earlier ones), so skipping it changes nothing.
+template <typename A>
+void count_stages(const AxisTables &t, int *nst_f, int *nst_b)
+{
+    *nst_f = 0;
+    *nst_b = 0;
+    for (int s = 0; s < gpssc::kMaxStages; ++s) {
+        if ((1 << s) >= t.lanes) break;
+        bool fnz = false, bnz = false;
+        for (int q = 0; q < t.lanes; ++q) {
+            const cplx f = t.scan[(size_t)s * t.lanes + q];
+            const cplx b = t.scan[(size_t)(gpssc::kMaxStages + s) * t.lanes + q];
+            if ((A)f.real() != (A)0 || (A)f.imag() != (A)0) fnz = true;
+            if ((A)b.real() != (A)0 || (A)b.imag() != (A)0) bnz = true;
+        }
+        if (fnz) *nst_f = s + 1;
+        if (bnz) *nst_b = s + 1;
+    }
+}
+
+template <typename A>
+cx<A> to_cx(cplx v) { return cx<A>{(A)v.real(), (A)v.imag()}; }
+
+// Device image of the tables of the three axes, in the arithmetic type.
+// x pivots are stored [chunk][64] so the per-lane reads coalesce; y/z pivots
+// position-major (all lanes of a row of the block read the same entry).
+template <typename A>
+std::vector<unsigned char> pack_tables(const AxisTables ax[3], size_t off[6])
+{
+    std::vector<cx<A>> v;
+    // x pivots
+    off[0] = v.size();
+    for (int c = 0; c < ax[0].chunk; ++c)
+        for (int l = 0; l < gpssc::kWave; ++l)
+            v.push_back(to_cx<A>(ax[0].m[(size_t)l * ax[0].chunk + c]));
+    off[1] = v.size();
+    for (const cplx &s : ax[0].scan) v.push_back(to_cx<A>(s));
+    for (int a = 1; a < 3; ++a) {
+        off[2 * a] = v.size();
+        for (const cplx &m : ax[a].m) v.push_back(to_cx<A>(m));
+        off[2 * a + 1] = v.size();
+        for (const cplx &s : ax[a].scan) v.push_back(to_cx<A>(s));
+    }
+    std::vector<unsigned char> bytes(v.size() * sizeof(cx<A>));
+    std::memcpy(bytes.data(), v.data(), bytes.size());
+    for (int q = 0; q < 6; ++q) off[q] *= sizeof(cx<A>);
+    return bytes;
+}
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bool valid_dtype(gp_dtype d) { return d == GP_C128 || d == GP_C64 || d == GP_C64_F64; }
+
+bool valid_grid(const int64_t grid[3])
+{
+    if (!grid) return false;
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 1) return false;
+    return true;
+}
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) hipSetDevice(dev);
+        dev_ = dev;
+    }
+    ~DeviceGuard()
+    {
+        if (prev_ >= 0 && prev_ != dev_) hipSetDevice(prev_);
+    }
+
+  private:
+    int prev_ = -1, dev_ = 0;
+};
+
+}  // namespace
+
+struct gp_plan {
+    int64_t n[3];
+    double dx[3];
+    double dt, omega[3], g;
+    gp_mode mode;
+    gp_dtype dtype;
+    hipStream_t stream;
+    int device;
+
+    AxisTables ax[3];
+    int xt_y, xt_z;
+    int nst_f[3], nst_b[3];
+
+    unsigned char *d_tables = nullptr;
+    size_t tab_off[6];
+    double *d_partials = nullptr;   // z-sweep norm partials
+    int n_zblocks = 0;
+    double *d_obs_partials = nullptr;
+    int n_obs_blocks = 0;
+    double *d_scale = nullptr;
+    int *d_flag = nullptr;
+    double *d_sums = nullptr;
+    double *h_sums = nullptr;   // pinned
+    int *h_flag = nullptr;      // pinned
+
+    int64_t steps_done = 0;
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> pool;
+
+    gpssc::XArgs<double> xd;
+    gpssc::XArgs<float> xf;
+    gpssc::SArgs<double> sd[2];
+    gpssc::SArgs<float> sf[2];
+};
+
+namespace {
+
+template <typename A>
+void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
+{
+    x.nx = (int)p->n[0];
+    x.ny = (int)p->n[1];
+    x.nz = (int)p->n[2];
+    x.nst_f = p->nst_f[0];
+    x.nst_b = p->nst_b[0];
+    x.c0x = (A)(0.5 * (double)(p->n[0] - 1));
+    x.c0y = (A)(0.5 * (double)(p->n[1] - 1));
+    x.c0z = (A)(0.5 * (double)(p->n[2] - 1));
+    x.dx = (A)p->dx[0];
+    x.dy = (A)p->dx[1];
+    x.dz = (A)p->dx[2];
+    x.hgx = (A)(0.5 * p->omega[0] * p->omega[0]);
+    x.hgy = (A)(0.5 * p->omega[1] * p->omega[1]);
+    x.hgz = (A)(0.5 * p->omega[2] * p->omega[2]);
+    x.dt = (A)p->dt;
+    x.g = (A)p->g;
+    x.o = to_cx<A>(p->ax[0].o);
+    x.rd = to_cx<A>(p->ax[0].rd);
+    x.ro = to_cx<A>(p->ax[0].ro);
+    for (int a = 1; a < 3; ++a) {
+        gpssc::SArgs<A> &t = s[a - 1];
+        t.nx = (int)p->n[0];
+        t.n = (int)p->n[a];
+        t.lanes = p->ax[a].lanes;
+        t.nst_f = p->nst_f[a];
+        t.nst_b = p->nst_b[a];
+        t.stride = a == 1 ? p->n[0] : p->n[0] * p->n[1];
+        t.outer_stride = a == 1 ? p->n[0] * p->n[1] : p->n[0];
+        t.o = to_cx<A>(p->ax[a].o);
+        t.rd = to_cx<A>(p->ax[a].rd);
+        t.ro = to_cx<A>(p->ax[a].ro);
+    }
+}
+
+hipEvent_t take_event(gp_plan *p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one launcher, bracketed by events while profiling.
+template <typename F>
+hipError_t timed(gp_plan *p, int cls, F &&launch)
+{
+    if (!p->profiling) return launch();
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, p->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+    p->prof.push_back(ProfRec{cls, a, b});
+    return e;
+}
+
+size_t footprint(const int64_t grid[3], gp_dtype dtype, int *xt_y, int *xt_z)
+{
+    int c[3], l[3];
+    for (int a = 0; a < 3; ++a)
+        if (!sweep_shape(grid[a], a, &c[a], &l[a])) return 0;
+    const size_t cs = dtype == GP_C64 ? 8 : 16;   // table entries: complex<float> or <double>
+    size_t tab = (size_t)c[0] * gpssc::kWave + 2 * gpssc::kMaxStages * gpssc::kWave;
+    for (int a = 1; a < 3; ++a) tab += (size_t)c[a] * l[a] + 2 * gpssc::kMaxStages * l[a];
+    tab *= cs;
+    const int xy = strided_columns(grid[0], l[1]);
+    const int xz = strided_columns(grid[0], l[2]);
+    if (xt_y) *xt_y = xy;
+    if (xt_z) *xt_z = xz;
+    const size_t zblocks = (size_t)((grid[0] + xz - 1) / xz) * (size_t)grid[1];
+    const size_t oblocks = (size_t)gpssc::obs_num_blocks((int)grid[0], (int)grid[1]);
+    return tab + zblocks * 8 + oblocks * gpssc::OBS_NSUMS * 8 + 8 + 8 + gpssc::OBS_NSUMS * 8;
+}
+
+void release(gp_plan *p)
+{
+    if (!p) return;
+    for (ProfRec &r : p->prof) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : p->pool) hipEventDestroy(e);
+    if (p->d_tables) hipFree(p->d_tables);
+    if (p->d_partials) hipFree(p->d_partials);
+    if (p->d_obs_partials) hipFree(p->d_obs_partials);
+    if (p->d_scale) hipFree(p->d_scale);
+    if (p->d_flag) hipFree(p->d_flag);
+    if (p->d_sums) hipFree(p->d_sums);
+    if (p->h_sums) hipHostFree(p->h_sums);
+    if (p->h_flag) hipHostFree(p->h_flag);
+    delete p;
+}
+
+gp_status check_psi(const gp_plan *p, const void *psi, int64_t elems)
+{
+    if (!psi) return fail(GP_ERR_INVALID, "psi is NULL");
+    const int64_t want = p->n[0] * p->n[1] * p->n[2];
+    if (elems != want)
+        return fail(GP_ERR_INVALID, "psi holds " + std::to_string(elems) + " elements, the grid needs " +
+                                        std::to_string(want));
+    const uintptr_t align = p->dtype == GP_C128 ? 16 : 8;
+    if ((uintptr_t)psi % align != 0) return fail(GP_ERR_INVALID, "psi is misaligned");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, psi);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GP_ERR_INVALID, "psi is not a device pointer");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(GP_ERR_INVALID, "psi is not device memory");
+    if (attr.device != p->device) return fail(GP_ERR_INVALID, "psi lives on another device than the plan");
+    return GP_OK;
+}
+
+gp_status read_flag(gp_plan *p)
+{
+    hipError_t e = hipMemcpyAsync(p->h_flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(e, "synchronising the plan's stream");
+    if (*p->h_flag) {
+        *p->h_flag = 0;
+        e = hipMemcpyAsync(p->d_flag, p->h_flag, sizeof(int), hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return fail_hip(e, "clearing the error flag");
+        return fail(GP_ERR_NONFINITE, "the norm became zero or non-finite during imaginary-time steps");
+    }
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gp_status_string(gp_status s)
+{
+    switch (s) {
+    case GP_OK: return "ok";
+    case GP_ERR_INVALID: return "invalid argument";
+    case GP_ERR_NOMEM: return "out of device memory";
+    case GP_ERR_DEVICE: return "device error";
+    case GP_ERR_NONFINITE: return "non-finite or zero norm";
+    case GP_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *gp_last_error(void) { return g_last_error.c_str(); }
+
+gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *lanes)
+{
+    if (!chunk || !lanes || axis < 0 || axis > 2 || !valid_dtype(dtype))
+        return fail(GP_ERR_INVALID, "bad gp_sweep_shape arguments");
+    if (n < 1) return fail(GP_ERR_INVALID, "line length must be >= 1");
+    if (!sweep_shape(n, axis, chunk, lanes)) return fail(GP_ERR_UNSUPPORTED, "line too long");
+    return GP_OK;
+}
+
+gp_status gp_sweep_tables(int64_t n, double dx, double dt, gp_mode mode, int chunk, int lanes,
+                          double *m, size_t m_len, double *chunkprod, size_t chunkprod_len,
+                          double *scan, size_t scan_len, double *coef, size_t coef_len)
+{
+    if (n < 1 || !finite_pos(dx) || !finite_pos(dt) || (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) ||
+        chunk < 1 || lanes < 1 || (int64_t)chunk * lanes < n || lanes > gpssc::kWave)
+        return fail(GP_ERR_INVALID, "bad gp_sweep_tables arguments");
+    const size_t npad = (size_t)chunk * lanes;
+    if (!m || m_len < 2 * npad || !chunkprod || chunkprod_len < 2 * (size_t)lanes || !scan ||
+        scan_len < 2 * 2 * (size_t)gpssc::kMaxStages * lanes || !coef || coef_len < 8)
+        return fail(GP_ERR_INVALID, "gp_sweep_tables output buffer too short");
+    AxisTables t;
+    build_axis(n, dx, dt, mode == GP_MODE_REAL, chunk, lanes, t);
+    for (size_t i = 0; i < npad; ++i) {
+        m[2 * i] = t.m[i].real();
+        m[2 * i + 1] = t.m[i].imag();
+    }
+    for (int q = 0; q < lanes; ++q) {
+        chunkprod[2 * q] = t.chunkprod[(size_t)q].real();
+        chunkprod[2 * q + 1] = t.chunkprod[(size_t)q].imag();
+    }
+    for (size_t i = 0; i < t.scan.size(); ++i) {
+        scan[2 * i] = t.scan[i].real();
+        scan[2 * i + 1] = t.scan[i].imag();
+    }
+    const cplx c4[4] = {t.b, t.o, t.rd, t.ro};
+    for (int q = 0; q < 4; ++q) {
+        coef[2 * q] = c4[q].real();
+        coef[2 * q + 1] = c4[q].imag();
+    }
+    return GP_OK;
+}
+
+size_t gp_plan_footprint_bytes(const int64_t grid[3], gp_dtype dtype)
+{
+    if (!valid_grid(grid) || !valid_dtype(dtype)) return 0;
+    return footprint(grid, dtype, nullptr, nullptr);
+}
+
+gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, double gamma,
+                         double nu, double lambda, double g, gp_mode mode, gp_dtype dtype,
+                         void *hip_stream, gp_plan **out)
+{
+    if (!out) return fail(GP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!valid_grid(grid)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
+    if (!dx || !finite_pos(dx[0]) || !finite_pos(dx[1]) || !finite_pos(dx[2]))
+        return fail(GP_ERR_INVALID, "dx must be finite and > 0");
+    if (!finite_pos(dt)) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
+    const double om[3] = {gamma, nu, lambda};
+    for (double w : om)
+        if (!std::isfinite(w) || w < 0.0) return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+    if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
+    if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
+    if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
+    int chunk[3], lanes[3];
+    for (int a = 0; a < 3; ++a)
+        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a]))
+            return fail(GP_ERR_UNSUPPORTED, "grid line too long (Nx <= 1024, Ny, Nz <= 1024)");
+    if (grid[1] * grid[2] > 0x7fffffffLL || grid[1] > 65535 || grid[2] > 65535)
+        return fail(GP_ERR_UNSUPPORTED, "too many grid lines for one launch");
+
+    gp_plan *p = new (std::nothrow) gp_plan();
+    if (!p) return fail(GP_ERR_NOMEM, "host allocation failed");
+    for (int a = 0; a < 3; ++a) {
+        p->n[a] = grid[a];
+        p->dx[a] = dx[a];
+        p->omega[a] = om[a];
+    }
+    p->dt = dt;
+    p->g = g;
+    p->mode = mode;
+    p->dtype = dtype;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        release(p);
+        return fail_hip(e, "hipGetDevice");
+    }
+
+    const bool real = mode == GP_MODE_REAL;
+    for (int a = 0; a < 3; ++a) build_axis(grid[a], dx[a], dt, real, chunk[a], lanes[a], p->ax[a]);
+    for (int a = 0; a < 3; ++a) {
+        if (dtype == GP_C64)
+            count_stages<float>(p->ax[a], &p->nst_f[a], &p->nst_b[a]);
+        else
+            count_stages<double>(p->ax[a], &p->nst_f[a], &p->nst_b[a]);
+    }
+    footprint(grid, dtype, &p->xt_y, &p->xt_z);
+    std::vector<unsigned char> tab = dtype == GP_C64 ? pack_tables<float>(p->ax, p->tab_off)
+                                                     : pack_tables<double>(p->ax, p->tab_off);
+    p->n_zblocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
+    p->n_obs_blocks = gpssc::obs_num_blocks((int)grid[0], (int)grid[1]);
+
+#define GP_ALLOC(ptr, bytes)                                                    \
+    do {                                                                        \
+        e = hipMalloc((void **)&(ptr), (bytes));                                \
+        if (e != hipSuccess) {                                                  \
+            (void)hipGetLastError();                                            \
+            release(p);                                                         \
+            return e == hipErrorOutOfMemory ? fail(GP_ERR_NOMEM, "hipMalloc failed") \
+                                            : fail_hip(e, "hipMalloc");         \
+        }                                                                       \
+    } while (0)
+    GP_ALLOC(p->d_tables, tab.size());
+    GP_ALLOC(p->d_partials, sizeof(double) * (size_t)p->n_zblocks);
+    GP_ALLOC(p->d_obs_partials, sizeof(double) * gpssc::OBS_NSUMS * (size_t)p->n_obs_blocks);
+    GP_ALLOC(p->d_scale, sizeof(double));
+    GP_ALLOC(p->d_flag, sizeof(int));
+    GP_ALLOC(p->d_sums, sizeof(double) * gpssc::OBS_NSUMS);
+#undef GP_ALLOC
+    e = hipHostMalloc((void **)&p->h_sums, sizeof(double) * gpssc::OBS_NSUMS, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&p->h_flag, sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(p);
+        return fail_hip(e, "hipHostMalloc");
+    }
+    *p->h_flag = 0;
+    e = hipMemcpyAsync(p->d_tables, tab.data(), tab.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_flag, p->h_flag, sizeof(int), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        release(p);
+        return fail_hip(e, "uploading the tables");
+    }
+    fill_args<double>(p, p->xd, p->sd);
+    fill_args<float>(p, p->xf, p->sf);
+    *out = p;
+    return GP_OK;
+}
+
+gp_status gp_plan_destroy(gp_plan *plan)
+{
+    if (!plan) return GP_OK;
+    {
+        DeviceGuard guard(plan->device);
+        hipStreamSynchronize(plan->stream);
+        release(plan);
+    }
+    return GP_OK;
+}
+
+gp_status gp_set_g(gp_plan *plan, double g)
+{
+    if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
+    plan->g = g;
+    plan->xd.g = g;
+    plan->xf.g = (float)g;
+    return GP_OK;
+}
+
+gp_status gp_set_stream(gp_plan *plan, void *hip_stream)
+{
+    if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
+    plan->stream = static_cast<hipStream_t>(hip_stream);
+    return GP_OK;
+}
+
+gp_status gp_step(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (nsteps < 0) return fail(GP_ERR_INVALID, "nsteps must be >= 0");
+    DeviceGuard guard(p->device);
+    gp_status st = check_psi(p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    if (nsteps == 0) return GP_OK;
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(p->dtype);
+    const bool c64 = p->dtype != GP_C128;   // complex64 storage
+    const bool a32 = p->dtype == GP_C64;    // FP32 arithmetic
+    const bool real = p->mode == GP_MODE_REAL;
+    const void *xargs = a32 ? (const void *)&p->xf : (const void *)&p->xd;
+    const void *yargs = a32 ? (const void *)&p->sf[0] : (const void *)&p->sd[0];
+    const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
+    const unsigned char *T = p->d_tables;
+    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
+        e = timed(p, GP_KERNEL_NU_X, [&] {
+            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, psi, xargs, T + p->tab_off[0],
+                                      T + p->tab_off[1], scale, p->stream);
+        });
+        if (e != hipSuccess) break;
+        e = timed(p, GP_KERNEL_Y, [&] {
+            return gpssc::launch_strided(prec, p->ax[1].chunk, p->xt_y, (int)p->n[2], psi, yargs,
+                                         T + p->tab_off[2], T + p->tab_off[3], nullptr, p->stream);
+        });
+        if (e != hipSuccess) break;
+        e = timed(p, GP_KERNEL_Z, [&] {
+            return gpssc::launch_strided(prec, p->ax[2].chunk, p->xt_z, (int)p->n[1], psi, zargs,
+                                         T + p->tab_off[4], T + p->tab_off[5],
+                                         real ? nullptr : p->d_partials, p->stream);
+        });
+        if (e != hipSuccess || real) continue;
+        e = timed(p, GP_KERNEL_NORM, [&] {
+            return gpssc::launch_norm_finalize(p->d_partials, p->n_zblocks, dv, p->d_scale,
+                                               p->d_flag, p->stream);
+        });
+    }
+    if (e == hipSuccess && !real) {
+        const int64_t elems = p->n[0] * p->n[1] * p->n[2];
+        e = timed(p, GP_KERNEL_SCALE,
+                  [&] { return gpssc::launch_scale(c64, psi, elems, p->d_scale, p->stream); });
+    }
+    if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
+    p->steps_done += nsteps;
+    return GP_OK;
+}
+
+gp_status gp_sync(gp_plan *p)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    DeviceGuard guard(p->device);
+    return read_flag(p);
+}
+
+gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs *out)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (!out) return fail(GP_ERR_INVALID, "out is NULL");
+    DeviceGuard guard(p->device);
+    gp_status st = check_psi(p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    const gp_status earlier = read_flag(p);
+    if (earlier == GP_ERR_DEVICE) return earlier;
+
+    gpssc::ObsArgs<double> a;
+    a.nx = (int)p->n[0];
+    a.ny = (int)p->n[1];
+    a.nz = (int)p->n[2];
+    a.c0x = 0.5 * (double)(p->n[0] - 1);
+    a.c0y = 0.5 * (double)(p->n[1] - 1);
+    a.c0z = 0.5 * (double)(p->n[2] - 1);
+    a.dx = p->dx[0];
+    a.dy = p->dx[1];
+    a.dz = p->dx[2];
+    a.hgx = 0.5 * p->omega[0] * p->omega[0];
+    a.hgy = 0.5 * p->omega[1] * p->omega[1];
+    a.hgz = 0.5 * p->omega[2] * p->omega[2];
+    hipError_t e = timed(p, GP_KERNEL_OBS, [&] {
+        return gpssc::launch_observables(p->dtype != GP_C128, psi, a, p->d_obs_partials, p->d_sums,
+                                         p->stream);
+    });
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_sums, p->d_sums, sizeof(double) * gpssc::OBS_NSUMS,
+                           hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(e, "computing observables");
+
+    const double *S = p->h_sums;
+    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
+    const double norm = dv * S[gpssc::OBS_DENS];
+    const double kin = 0.5 * dv *
+                       (S[gpssc::OBS_LINKX] / (p->dx[0] * p->dx[0]) + S[gpssc::OBS_LINKY] / (p->dx[1] * p->dx[1]) +
+                        S[gpssc::OBS_LINKZ] / (p->dx[2] * p->dx[2]));
+    const double pot = dv * S[gpssc::OBS_POT];
+    const double inter = p->g * dv * S[gpssc::OBS_QUART];
+    out->norm = norm;
+    out->kinetic = kin / norm;
+    out->potential = pot / norm;
+    out->interaction = inter / (norm * norm);
+    out->energy = out->kinetic + out->potential + 0.5 * out->interaction;
+    out->mu = out->kinetic + out->potential + out->interaction;
+    double r2 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const double m2 = dv * S[gpssc::OBS_M2X + q] / norm;
+        out->rms[q] = std::sqrt(m2);
+        out->mean[q] = dv * S[gpssc::OBS_M1X + q] / norm;
+        r2 += m2;
+    }
+    out->rms_r = std::sqrt(r2);
+    out->steps_done = p->steps_done;
+    if (earlier != GP_OK) return earlier;
+    const double all[] = {out->norm, out->mu, out->energy, out->rms[0], out->rms[1], out->rms[2],
+                          out->rms_r, out->mean[0], out->mean[1], out->mean[2], out->kinetic,
+                          out->potential, out->interaction};
+    bool ok = norm > 0.0;
+    for (double v : all) ok = ok && std::isfinite(v);
+    if (!ok) return fail(GP_ERR_NONFINITE, "psi has a zero or non-finite norm or observable");
+    return GP_OK;
+}
+
+gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
+{
+    if (!p || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_plan_describe arguments");
+    std::snprintf(buf, len,
+                  "grid %lldx%lldx%lld %s %s | x: chunk %d, 64 lanes, stages %d/%d | "
+                  "y: chunk %d, %d lanes, %d cols, stages %d/%d | z: chunk %d, %d lanes, %d cols, stages %d/%d",
+                  (long long)p->n[0], (long long)p->n[1], (long long)p->n[2],
+                  p->mode == GP_MODE_REAL ? "real" : "imag", p->dtype == GP_C64 ? "c64" : (p->dtype == GP_C64_F64 ? "c64/f64" : "c128"),
+                  p->ax[0].chunk, p->nst_f[0], p->nst_b[0], p->ax[1].chunk, p->ax[1].lanes, p->xt_y,
+                  p->nst_f[1], p->nst_b[1], p->ax[2].chunk, p->ax[2].lanes, p->xt_z, p->nst_f[2],
+                  p->nst_b[2]);
+    return GP_OK;
+}
+
+gp_status gp_profile_enable(gp_plan *p, int on)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    p->profiling = on != 0;
+    return GP_OK;
+}
+
+gp_status gp_profile_read(gp_plan *p, double *ms, int64_t *launches)
+{
+    if (!p || !ms || !launches) return fail(GP_ERR_INVALID, "bad gp_profile_read arguments");
+    DeviceGuard guard(p->device);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(e, "synchronising the plan's stream");
+    for (int k = 0; k < GP_KERNEL_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (ProfRec &r : p->prof) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            ms[r.cls] += t;
+            launches[r.cls] += 1;
+        }
+        p->pool.push_back(r.a);
+        p->pool.push_back(r.b);
+    }
+    p->prof.clear();
+    return GP_OK;
+}
+
+}  // extern "C"

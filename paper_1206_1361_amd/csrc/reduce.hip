@@ -1,0 +1,198 @@
+// reduce.hip -- calcnorm finalisation, the end-of-call scaling, and the
+// calcmuen / calcrms sums.
+//
+// Paper: "Summary of revisions" names calcnorm (normalisation) and calcmuen,
+// calcrms (chemical potential, energy and rms sizes) among the routines that
+// carry a time step and its diagnostics.  Every sum here is FP64 and formed
+// in a fixed order (per thread, then a fixed LDS tree per block, then a
+// fixed-order sum over the blocks), so results are bitwise reproducible.
+#include "gp_internal.h"
+
+namespace gpssc {
+
+constexpr int kReduceThreads = 256;
+
+// Fixed-order sum of v over a block of kReduceThreads threads; the result is
+// valid in thread 0.
+__device__ double block_sum(double v, double *red)
+{
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+calcnorm_finalize_kernel(const double *__restrict__ partials, int n, double dv,
+                         double *__restrict__ scale, int *__restrict__ flag)
+{
+    __shared__ double red[kReduceThreads];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += kReduceThreads) acc += partials[b];
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        const double norm = dv * sum;
+        const bool ok = norm > 0.0 && isfinite(norm);
+        *scale = ok ? 1.0 / sqrt(norm) : (double)NAN;
+        if (!ok) flag[0] = 1;
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kReduceThreads)
+scale_kernel(S *__restrict__ psi, int64_t elems, const double *__restrict__ scale)
+{
+    using R = typename storage_traits<S>::real;
+    const R s = (R)(*scale);
+    const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
+    for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
+        S v = psi[p];
+        v.x *= s;
+        v.y *= s;
+        psi[p] = v;
+    }
+}
+
+// Observables: block (64, 4) covers 64 x 4 columns (i, j) and walks z.  Each
+// point adds |psi|^2, V|psi|^2, |psi|^4, x|psi|^2 ..., z^2|psi|^2 and the
+// squared difference to the next node along each axis (zero beyond the
+// last node); the link to the zero before the first node is added at the
+// first node.
+constexpr int kObsX = 64, kObsY = 4;
+
+template <typename S>
+__global__ void __launch_bounds__(kObsX * kObsY)
+calcmuen_rms_kernel(const S *__restrict__ psi, const ObsArgs<double> a,
+                    double *__restrict__ partials)
+{
+    __shared__ double red[kReduceThreads];
+    const int tx = threadIdx.x % kObsX, ty = threadIdx.x / kObsX;
+    const int i = blockIdx.x * kObsX + tx;
+    const int j = blockIdx.y * kObsY + ty;
+    double acc[OBS_NSUMS];
+#pragma unroll
+    for (int q = 0; q < OBS_NSUMS; ++q) acc[q] = 0.0;
+
+    if (i < a.nx && j < a.ny) {
+        const int64_t plane = (int64_t)a.nx * a.ny;
+        const double x = ((double)i - a.c0x) * a.dx;
+        const double y = ((double)j - a.c0y) * a.dy;
+        const double vxy = a.hgx * x * x + a.hgy * y * y;
+        double prev_re = 0.0, prev_im = 0.0;  // node k-1 (zero before the first)
+        const S *col = psi + (int64_t)j * a.nx + i;
+        for (int k = 0; k < a.nz; ++k) {
+            const S v = col[(int64_t)k * plane];
+            const double re = v.x, im = v.y;
+            const double w = re * re + im * im;
+            const double z = ((double)k - a.c0z) * a.dz;
+            acc[OBS_DENS] += w;
+            acc[OBS_POT] += (vxy + a.hgz * z * z) * w;
+            acc[OBS_QUART] += w * w;
+            acc[OBS_M1X] += x * w;
+            acc[OBS_M1Y] += y * w;
+            acc[OBS_M1Z] += z * w;
+            acc[OBS_M2X] += x * x * w;
+            acc[OBS_M2Y] += y * y * w;
+            acc[OBS_M2Z] += z * z * w;
+            // x link to i+1 (and the ghost link before i = 0)
+            double nre = 0.0, nim = 0.0;
+            if (i + 1 < a.nx) {
+                const S n = col[(int64_t)k * plane + 1];
+                nre = n.x;
+                nim = n.y;
+            }
+            acc[OBS_LINKX] += (nre - re) * (nre - re) + (nim - im) * (nim - im);
+            if (i == 0) acc[OBS_LINKX] += w;
+            // y link to j+1
+            nre = 0.0;
+            nim = 0.0;
+            if (j + 1 < a.ny) {
+                const S n = col[(int64_t)k * plane + a.nx];
+                nre = n.x;
+                nim = n.y;
+            }
+            acc[OBS_LINKY] += (nre - re) * (nre - re) + (nim - im) * (nim - im);
+            if (j == 0) acc[OBS_LINKY] += w;
+            // z link from k-1 (the k = 0 term is the ghost link)
+            acc[OBS_LINKZ] += (re - prev_re) * (re - prev_re) + (im - prev_im) * (im - prev_im);
+            prev_re = re;
+            prev_im = im;
+        }
+        acc[OBS_LINKZ] += prev_re * prev_re + prev_im * prev_im;  // ghost beyond the last node
+    }
+
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int q = 0; q < OBS_NSUMS; ++q) {
+        const double s = block_sum(acc[q], red);
+        if (threadIdx.x == 0) partials[b * OBS_NSUMS + q] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+obs_finalize_kernel(const double *__restrict__ partials, int nblocks, double *__restrict__ sums)
+{
+    __shared__ double red[kReduceThreads];
+    for (int q = 0; q < OBS_NSUMS; ++q) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kReduceThreads)
+            acc += partials[(int64_t)b * OBS_NSUMS + q];
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) sums[q] = s;
+    }
+}
+
+hipError_t launch_norm_finalize(const double *partials, int n, double dv, double *scale,
+                                int *flag, hipStream_t stream)
+{
+    hipLaunchKernelGGL(calcnorm_finalize_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
+                       partials, n, dv, scale, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(bool c64, void *psi, int64_t elems, const double *scale,
+                        hipStream_t stream)
+{
+    int64_t blocks = (elems + kReduceThreads - 1) / kReduceThreads;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    if (c64)
+        hipLaunchKernelGGL(scale_kernel<float2>, dim3((unsigned)blocks), dim3(kReduceThreads), 0,
+                           stream, static_cast<float2 *>(psi), elems, scale);
+    else
+        hipLaunchKernelGGL(scale_kernel<double2>, dim3((unsigned)blocks), dim3(kReduceThreads), 0,
+                           stream, static_cast<double2 *>(psi), elems, scale);
+    return hipGetLastError();
+}
+
+int obs_num_blocks(int nx, int ny)
+{
+    return ((nx + kObsX - 1) / kObsX) * ((ny + kObsY - 1) / kObsY);
+}
+
+hipError_t launch_observables(bool c64, const void *psi, const ObsArgs<double> &args,
+                              double *partials, double *sums, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((args.nx + kObsX - 1) / kObsX),
+                    (unsigned)((args.ny + kObsY - 1) / kObsY));
+    const dim3 block(kObsX * kObsY);
+    if (c64)
+        hipLaunchKernelGGL(calcmuen_rms_kernel<float2>, grid, block, 0, stream,
+                           static_cast<const float2 *>(psi), args, partials);
+    else
+        hipLaunchKernelGGL(calcmuen_rms_kernel<double2>, grid, block, 0, stream,
+                           static_cast<const double2 *>(psi), args, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(obs_finalize_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
+                       partials, (int)grid.x * (int)grid.y, sums);
+    return hipGetLastError();
+}
+
+}  // namespace gpssc

@@ -57,24 +57,37 @@ def thomas_fermi(grid, dx, omega, g: float, noise: float = 0.0, seed: int = 0,
                  floor: float = 0.0) -> np.ndarray:
     """sqrt(max(0, (mu_TF - V)/g)) + complex Gaussian noise of std `noise` per
     component, normalised.  `floor` adds a small Gaussian tail so the state
-    has no exact zeros (optional)."""
-    x, y, z = mesh(grid, dx)
-    V = 0.5 * (omega[0] ** 2 * x * x + omega[1] ** 2 * y * y + omega[2] ** 2 * z * z)
+    has no exact zeros (optional).  Built one z plane at a time (the noise
+    of plane k is drawn after that of plane k-1: real parts, then imaginary
+    parts), so large grids need no grid-sized temporaries."""
+    nx, ny, nz = grid
+    x = axis(nx, dx[0])[None, :]
+    y = axis(ny, dx[1])[:, None]
+    z = axis(nz, dx[2])
+    vxy = 0.5 * (omega[0] ** 2 * x * x + omega[1] ** 2 * y * y)
     mu = mu_thomas_fermi(omega, g)
-    psi = np.sqrt(np.maximum(0.0, (mu - V) / g)).astype(np.complex128)
-    if floor:
-        psi += floor * np.exp(-V / max(mu, 1e-300))
-    if noise:
-        rng = np.random.default_rng(seed)
-        shape = psi.shape
-        psi += noise * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    rng = np.random.default_rng(seed) if noise else None
+    psi = np.empty((nz, ny, nx), dtype=np.complex128)
+    for k in range(nz):
+        V = vxy + 0.5 * omega[2] ** 2 * z[k] * z[k]
+        amp = np.sqrt(np.maximum(0.0, (mu - V) / g))
+        if floor:
+            amp = amp + floor * np.exp(-V / max(mu, 1e-300))
+        plane = psi[k]
+        plane.real = amp
+        plane.imag = 0.0
+        if noise:
+            plane.real += noise * rng.standard_normal((ny, nx))
+            plane.imag += noise * rng.standard_normal((ny, nx))
     return normalise(psi, dx)
 
 
 def phase_noise(psi: np.ndarray, amplitude: float, seed: int) -> np.ndarray:
-    """psi * exp(i theta), theta ~ U(-amplitude, amplitude) per point (in place)."""
+    """psi * exp(i theta), theta ~ U(-amplitude, amplitude) per point (in
+    place), drawn one z plane at a time."""
     rng = np.random.default_rng(seed)
-    psi *= np.exp(1j * rng.uniform(-amplitude, amplitude, psi.shape))
+    for k in range(psi.shape[0]):
+        psi[k] *= np.exp(1j * rng.uniform(-amplitude, amplitude, psi.shape[1:]))
     return psi
 
 

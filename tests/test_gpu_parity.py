@@ -1,0 +1,247 @@
+"""GPU path vs the CPU FP64 oracle, element by element, through the C ABI.
+
+Tolerances (max |psi_gpu - psi_oracle| / max |psi_oracle|, and relative mu):
+  complex128 (FP64 arithmetic):              psi <= 1e-12, mu <= 1e-12
+  complex64 (FP32 storage, FP32 or FP64
+  arithmetic, FP64 reductions):              psi <= 1e-5,  mu <= 1e-7
+The chunked Thomas scheme and the deferred renormalisation reorder rounding
+relative to the oracle's sequential recursion, so results agree to rounding,
+not bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1206_1361_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1206_1361_amd as gp  # noqa: E402
+
+TOL = {"c128": (1e-12, 1e-12), "c64": (1e-5, 1e-7), "c64_f64": (1e-5, 1e-7)}
+# Norm and mu on the small synthetic grids: with complex64 storage every
+# sweep rounds each stored component by up to 2^-24 relative, and a grid of a
+# few points does not average these out, so after n steps (3 stores each)
+# the quadratic observables can move by ~2 (3n + 1) 2^-24 ~ 2.3e-6 (n = 6).
+TOL_OBS_SMALL = {"c128": 1e-12, "c64": 3e-6, "c64_f64": 3e-6}
+DTYPES = ["c128", "c64", "c64_f64"]
+MODES = {"imag": oracle.IMAG, "real": oracle.REAL}
+
+
+def to_dev(psi, dtype):
+    t = torch.from_numpy(psi)
+    if dtype.startswith("c64"):
+        t = t.to(torch.complex64)
+    return t.to("cuda").contiguous()
+
+
+def to_host(t):
+    return t.to(torch.complex128).cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def gpu_run(psi0, grid, dx, dt, omega, g, mode, dtype, nsteps, chunks=1):
+    psi = to_dev(psi0, dtype)
+    with gp.Plan(grid, dx, dt, *omega, g, mode=mode, dtype=dtype) as plan:
+        per = nsteps // chunks
+        done = 0
+        for c in range(chunks):
+            n = per if c < chunks - 1 else nsteps - done
+            plan.step(psi, n)
+            done += n
+        obs = plan.observables(psi)
+        plan.sync()
+    return to_host(psi), obs
+
+
+def oracle_run(psi0, dx, dt, omega, g, mode, nsteps):
+    psi = psi0.copy()
+    oracle.step(psi, dx, dt, omega, g, MODES[mode], nsteps)
+    return psi, oracle.observables(psi, dx, omega, g)
+
+
+def input_for(dtype, psi):
+    """The oracle starts from exactly the values the GPU holds."""
+    if dtype.startswith("c64"):
+        return psi.astype(np.complex64).astype(np.complex128)
+    return psi
+
+
+SMALL_GRIDS = [
+    (1, 1, 1), (5, 1, 1), (1, 6, 1), (1, 1, 7), (7, 5, 3), (33, 17, 9), (64, 64, 64),
+    (65, 70, 66), (130, 63, 97), (200, 129, 40),
+]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["imag", "real"])
+@pytest.mark.parametrize("grid", SMALL_GRIDS, ids=lambda g: "x".join(map(str, g)))
+def test_steps_match_oracle(grid, mode, dtype):
+    dx = (0.3, 0.25, 0.35)
+    omega = (1.0, 1.4, 2.0)
+    g = 12.0
+    dt = 0.05 if mode == "imag" else 0.01
+    psi0 = input_for(dtype, inputs.smooth_random_state(grid, dx, omega, seed=sum(grid)))
+    nsteps = 6
+    ref, robs = oracle_run(psi0, dx, dt, omega, g, mode, nsteps)
+    got, gobs = gpu_run(psi0, grid, dx, dt, omega, g, mode, dtype, nsteps, chunks=2)
+    tpsi, _ = TOL[dtype]
+    tobs = TOL_OBS_SMALL[dtype]
+    assert rel(got, ref) <= tpsi
+    assert abs(gobs["mu"] - robs["mu"]) <= tobs * abs(robs["mu"])
+    assert abs(gobs["norm"] - robs["norm"]) <= tobs * robs["norm"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_small_imaginary_time_workload(dtype):
+    """32^3, dx 0.25, dt 0.1 dx^2, trap (1, 1.4, 2), g 10, Gaussian, 200 steps."""
+    w = inputs.SMALL_IMAG
+    psi0 = input_for(dtype, inputs.initial_state(w))
+    ref, robs = oracle_run(psi0, w.dx, w.dt, w.omega, w.g, w.mode, w.steps)
+    got, gobs = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, w.mode, dtype, w.steps, chunks=4)
+    tpsi, tmu = TOL[dtype]
+    assert rel(got, ref) <= tpsi
+    for k in ("mu", "energy", "rms_x", "rms_y", "rms_z", "rms_r", "norm"):
+        assert abs(gobs[k] - robs[k]) <= tmu * abs(robs[k]), k
+    assert gobs["steps_done"] == w.steps
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_observables_match_oracle(dtype):
+    grid, dx, omega, g = (70, 45, 33), (0.2, 0.3, 0.25), (1.0, 1.4, 2.0), 7.5
+    psi0 = input_for(dtype, inputs.smooth_random_state(grid, dx, omega, seed=3) * 1.7)
+    robs = oracle.observables(psi0, dx, omega, g)
+    psi = to_dev(psi0, dtype)
+    with gp.Plan(grid, dx, 0.01, *omega, g, mode="real", dtype=dtype) as plan:
+        gobs = plan.observables(psi)
+    for k in oracle.OBS_NAMES:
+        tol = 1e-12 * max(abs(robs[k]), 1e-3)
+        assert abs(gobs[k] - robs[k]) <= tol, (k, gobs[k], robs[k])
+
+
+def test_quench_matches_oracle():
+    """g changes between queued steps (gp_set_g) exactly as in the oracle."""
+    grid, dx, omega = (48, 40, 32), (0.3,) * 3, (0.5, 1.0, 1.5)
+    psi0 = inputs.thomas_fermi(grid, dx, omega, 22.0, floor=1e-3)
+    inputs.phase_noise(psi0, 1e-3, 2)
+    dt = 0.002
+    ref = psi0.copy()
+    oracle.step(ref, dx, dt, omega, 22.0, oracle.REAL, 3)
+    oracle.step(ref, dx, dt, omega, 11.0, oracle.REAL, 5)
+    psi = to_dev(psi0, "c128")
+    with gp.Plan(grid, dx, dt, *omega, 22.0, mode="real") as plan:
+        plan.step(psi, 3)
+        plan.set_g(11.0)
+        plan.step(psi, 5)
+        plan.sync()
+    assert rel(to_host(psi), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("grid", [(1024, 3, 2), (3, 1024, 2), (2, 3, 1024), (1000, 7, 5)],
+                         ids=lambda g: "x".join(map(str, g)))
+@pytest.mark.parametrize("mode", ["imag", "real"])
+def test_longest_lines(grid, mode):
+    dx = (0.02, 0.3, 0.3) if grid[0] >= 1000 else ((0.3, 0.02, 0.3) if grid[1] >= 1000 else (0.3, 0.3, 0.02))
+    omega = (1.0, 1.0, 1.0)
+    psi0 = inputs.smooth_random_state(grid, dx, omega, seed=5)
+    dt = 0.01
+    ref, _ = oracle_run(psi0, dx, dt, omega, 3.0, mode, 3)
+    got, _ = gpu_run(psi0, grid, dx, dt, omega, 3.0, mode, "c128", 3)
+    assert rel(got, ref) <= 1e-12
+
+
+def test_weakly_dominant_systems_use_every_scan_stage():
+    """Large dt/dx^2 makes the Thomas carries decay slowly, so every
+    Kogge-Stone stage carries weight."""
+    grid, dx, omega = (256, 200, 130), (0.05,) * 3, (1.0, 1.0, 1.0)
+    psi0 = inputs.smooth_random_state(grid, (0.05,) * 3, omega, seed=7)
+    for mode, dt in (("imag", 0.5), ("real", 0.5)):
+        ref, _ = oracle_run(psi0, dx, dt, omega, 1.0, mode, 2)
+        got, _ = gpu_run(psi0, grid, dx, dt, omega, 1.0, mode, "c128", 2)
+        assert rel(got, ref) <= 1e-12, mode
+
+
+def test_zero_steps_changes_nothing():
+    grid, dx = (20, 10, 5), (0.3,) * 3
+    psi0 = inputs.random_state(grid, dx, seed=1)
+    got, _ = gpu_run(psi0, grid, dx, 0.01, (1, 1, 1), 1.0, "imag", "c128", 0)
+    assert np.array_equal(got, psi0)
+
+
+def test_results_are_bitwise_reproducible():
+    w = inputs.SMALL_IMAG
+    psi0 = inputs.initial_state(w)
+    a, oa = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, "imag", "c128", 50)
+    b, ob = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, "imag", "c128", 50)
+    assert np.array_equal(a, b)
+    assert oa == ob
+
+
+def test_runs_on_a_side_stream():
+    w = inputs.SMALL_IMAG
+    psi0 = inputs.initial_state(w)
+    ref, _ = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, "imag", "c128", 20)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        psi = to_dev(psi0, "c128")
+        with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode="imag") as plan:
+            plan.step(psi, 20)
+            out = psi.clone()
+    s.synchronize()
+    assert np.array_equal(to_host(out), ref)
+
+
+# ---------------------------------------------------------------- full sizes
+@pytest.fixture(scope="module")
+def large_initial():
+    w = inputs.LARGE_REAL
+    return inputs.initial_state(w)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_large_grid_one_step_full_comparison(large_initial, dtype):
+    """512x512x384: one real-time step in the benchmark's launch shapes,
+    compared over the whole grid."""
+    w = inputs.LARGE_REAL
+    psi0 = input_for(dtype, large_initial)
+    ref, robs = oracle_run(psi0, w.dx, w.dt, w.omega, w.g, w.mode, 1)
+    got, gobs = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, w.mode, dtype, 1)
+    tpsi, tmu = TOL[dtype]
+    assert rel(got, ref) <= tpsi
+    for k in ("norm", "mu", "energy", "rms_r"):
+        assert abs(gobs[k] - robs[k]) <= tmu * abs(robs[k]), k
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_large_grid_full_run_conserves_norm(large_initial, dtype):
+    """The benchmark's 500 real-time steps: the CN and phase sub-steps are
+    unitary, so the norm may only drift by rounding."""
+    w = inputs.LARGE_REAL
+    psi = to_dev(large_initial, dtype)
+    with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype=dtype) as plan:
+        n0 = plan.observables(psi)
+        plan.step(psi, w.steps)
+        n1 = plan.observables(psi)
+    drift = abs(n1["norm"] - n0["norm"])
+    print(f"norm drift over {w.steps} steps ({dtype}): {drift:.3e}")
+    assert drift <= (1e-11 if dtype == "c128" else 1e-4), drift
+    # Lie splitting does not conserve energy exactly; a loose sanity bound
+    assert abs(n1["energy"] - n0["energy"]) <= 1e-2 * abs(n0["energy"])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_quench_grid_full_comparison(dtype):
+    """240x200x160 real-time quench grid, 3 steps at g = 11, whole grid."""
+    w = inputs.QUENCH
+    psi0 = input_for(dtype, inputs.initial_state(w))
+    ref, robs = oracle_run(psi0, w.dx, w.dt, w.omega, w.g_after, w.mode, 3)
+    got, gobs = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g_after, w.mode, dtype, 3)
+    tpsi, tmu = TOL[dtype]
+    assert rel(got, ref) <= tpsi
+    assert abs(gobs["mu"] - robs["mu"]) <= tmu * abs(robs["mu"])

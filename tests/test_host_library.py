@@ -1,0 +1,201 @@
+"""Host-side checks of libgpssc that need no GPU: the exported C ABI, argument
+validation before any device call, the launch-shape policy, and the chunked
+Thomas scheme the sweep kernels run, replayed in numpy with the library's
+own coefficient tables and compared with a dense solve."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1206_1361_amd as gp
+from paper_1206_1361_amd import _binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "gpssc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gp.lib()
+    declared = header_functions()
+    assert declared, "no declarations found"
+    assert sorted(_binding.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_last_error():
+    L = gp.lib()
+    for code in range(6):
+        assert L.gp_status_string(code)
+    assert L.gp_status_string(99) == b"unknown status"
+    out = ctypes.c_void_p()
+    n = (ctypes.c_int64 * 3)(0, 4, 4)
+    d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    assert L.gp_plan_create(n, d, 0.01, 1.0, 1.0, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == 1
+    assert b"grid" in L.gp_last_error()
+    assert out.value is None
+
+
+BAD_CREATE = [
+    dict(grid=(0, 4, 4)), dict(grid=(4, -1, 4)), dict(dx=(0.1, 0.0, 0.1)), dict(dx=(0.1, float("nan"), 0.1)),
+    dict(dt=0.0), dict(dt=-1.0), dict(dt=float("inf")), dict(gamma=-1.0), dict(lam=float("nan")),
+    dict(g=float("inf")), dict(mode=7), dict(dtype=3),
+]
+
+
+@pytest.mark.parametrize("bad", BAD_CREATE)
+def test_plan_create_rejects_bad_arguments_before_any_device_call(bad):
+    args = dict(grid=(8, 8, 8), dx=(0.1, 0.1, 0.1), dt=0.01, gamma=1.0, nu=1.0, lam=1.0, g=1.0, mode=0, dtype=0)
+    args.update(bad)
+    L = gp.lib()
+    out = ctypes.c_void_p(1234)
+    n = (ctypes.c_int64 * 3)(*args["grid"])
+    d = (ctypes.c_double * 3)(*args["dx"])
+    st = L.gp_plan_create(n, d, args["dt"], args["gamma"], args["nu"], args["lam"], args["g"],
+                          args["mode"], args["dtype"], None, ctypes.byref(out))
+    assert st == _binding.ERR_INVALID
+    assert out.value is None
+
+
+def test_plan_create_rejects_unsupported_lengths():
+    L = gp.lib()
+    out = ctypes.c_void_p()
+    d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    for grid in ((1025, 8, 8), (8, 1025, 8), (8, 8, 4096)):
+        n = (ctypes.c_int64 * 3)(*grid)
+        assert L.gp_plan_create(n, d, 0.01, 1.0, 1.0, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == \
+            _binding.ERR_UNSUPPORTED
+
+
+def test_null_plan_arguments():
+    L = gp.lib()
+    assert L.gp_plan_destroy(None) == 0
+    assert L.gp_set_g(None, 1.0) == _binding.ERR_INVALID
+    assert L.gp_step(None, None, 0, 1) == _binding.ERR_INVALID
+    assert L.gp_sync(None) == _binding.ERR_INVALID
+    assert L.gp_observables(None, None, 0, None) == _binding.ERR_INVALID
+    assert L.gp_plan_create(None, None, 0.1, 1, 1, 1, 1, 0, 0, None, None) == _binding.ERR_INVALID
+
+
+def test_footprint():
+    assert gp.footprint_bytes((0, 8, 8)) == 0
+    small = gp.footprint_bytes((32, 32, 32))
+    large = gp.footprint_bytes((512, 512, 384))
+    assert 0 < small < large < 1 << 20        # tables + scratch only, not psi
+    assert gp.footprint_bytes((512, 512, 384), "c64") < large
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 63, 64, 65, 200, 240, 384, 511, 512, 1000, 1024])
+def test_sweep_shapes(n):
+    cx, lx = gp.sweep_shape(n, 0)
+    assert lx == 64 and cx * 64 >= n and (cx == 1 or (cx - 1) * 64 < n or cx in (10, 12, 14, 16))
+    for axis in (1, 2):
+        c, l = gp.sweep_shape(n, axis)
+        assert c * l >= n and l <= 64 and (l - 1) * c < n
+    with pytest.raises(gp.GPError):
+        gp.sweep_shape(2048, 1)
+
+
+def dense_cn_rhs_solve(n, tab, psi):
+    A = tab["b"] * np.eye(n) + tab["o"] * (np.eye(n, k=1) + np.eye(n, k=-1))
+    B = tab["rdiag"] * np.eye(n) + tab["roff"] * (np.eye(n, k=1) + np.eye(n, k=-1))
+    return np.linalg.solve(A, B @ psi)
+
+
+def chunked_solve(tab, n, chunk, lanes, psi, stages=None):
+    """The sweep kernels' scheme: per-chunk Thomas with zero carry, Kogge-Stone
+    over chunks with the library's stage multipliers, rerun from the carry."""
+    npad = chunk * lanes
+    u = np.zeros(npad, complex)
+    u[:n] = psi
+    left = np.concatenate([[0], u[:-1]])
+    right = np.concatenate([u[1:], [0]])
+    q = tab["rdiag"] * u + tab["roff"] * (left + right)
+    m = tab["m"]
+    a = -tab["o"] * m
+    mq = m * q
+    scan = tab["scan"]
+    if stages is None:
+        stages = [int(np.max(np.nonzero(np.any(scan[dr] != 0, axis=1))[0], initial=-1)) + 1 for dr in (0, 1)]
+
+    def local(carry, k, values, backward):
+        idx = range(k * chunk, (k + 1) * chunk)
+        idx = reversed(list(idx)) if backward else idx
+        t = carry
+        out = np.zeros(npad, complex)
+        for i in idx:
+            t = values[i] + a[i] * t
+            out[i] = t
+        return t, out
+
+    L = np.array([local(0, k, mq, False)[0] for k in range(lanes)])
+    F = L.copy()
+    for s in range(stages[0]):
+        d = 1 << s
+        F = np.array([F[k] + (scan[0, s, k] * F[k - d] if k >= d else 0) for k in range(lanes)])
+    dvals = np.zeros(npad, complex)
+    for k in range(lanes):
+        _, o = local(F[k - 1] if k > 0 else 0, k, mq, False)
+        dvals += o
+    U = np.array([local(0, k, dvals, True)[0] for k in range(lanes)])
+    R = U.copy()
+    for s in range(stages[1]):
+        d = 1 << s
+        R = np.array([R[k] + (scan[1, s, k] * R[k + d] if k + d < lanes else 0) for k in range(lanes)])
+    x = np.zeros(npad, complex)
+    for k in range(lanes):
+        _, o = local(R[k + 1] if k + 1 < lanes else 0, k, dvals, True)
+        x += o
+    return x[:n]
+
+
+@pytest.mark.parametrize("mode", ["imag", "real"])
+@pytest.mark.parametrize("n,dx,dt", [(1, 0.25, 0.006), (7, 0.25, 0.006), (32, 0.25, 0.00625),
+                                     (200, 0.1, 5e-5), (240, 0.1, 0.01), (384, 0.05, 1.25e-5),
+                                     (512, 0.05, 0.25), (97, 0.1, 1.0)])
+def test_chunked_thomas_with_library_tables_matches_dense_solve(mode, n, dx, dt):
+    rng = np.random.default_rng(n)
+    psi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for axis in (0, 1):
+        chunk, lanes = gp.sweep_shape(n, axis)
+        tab = gp.sweep_tables(n, dx, dt, mode, chunk, lanes)
+        assert np.all(tab["m"][n:] == 0)
+        ref = dense_cn_rhs_solve(n, tab, psi)
+        x = chunked_solve(tab, n, chunk, lanes, psi)
+        assert np.max(np.abs(x - ref)) <= 1e-14 * np.max(np.abs(ref))
+        # skipping the all-zero stages changes nothing
+        if lanes > 1:
+            full = chunked_solve(tab, n, chunk, lanes, psi, stages=[6, 6])
+            assert np.array_equal(full, x)
+
+
+def test_sweep_table_coefficients():
+    tab = gp.sweep_tables(10, 0.5, 0.1, "real", 1, 10)
+    kappa = 1j * 0.1 / (2 * 0.25)
+    assert tab["b"] == 1 + kappa and tab["o"] == -kappa / 2
+    assert tab["rdiag"] == 1 - kappa and tab["roff"] == kappa / 2
+    assert abs(tab["m"][0] - 1 / (1 + kappa)) < 1e-16
+    with pytest.raises(gp.GPError):
+        gp.sweep_tables(10, 0.5, 0.1, "real", 1, 5)     # chunk * lanes < n
+
+
+def test_gpu_path_and_oracle_share_no_code():
+    """The library and the oracle neither import nor include each other."""
+    pkg = os.path.join(ROOT, "paper_1206_1361_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "gpo." not in text and "gpo_" not in text, f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1206_1361_amd" not in text and "gpssc" not in text, f
