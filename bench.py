@@ -23,7 +23,6 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
-import math
 import os
 import pathlib
 import sys
@@ -37,10 +36,11 @@ sys.path.insert(0, str(ROOT))
 METRIC = "grid-point SSCN steps/sec (FP64 vs FP32) as % HBM roofline; p50/p99 solve latency"
 UNIT = "grid-point-steps/s"
 HBM_PEAK_GBS = 8000.0
+_COMMON = ["paper_1206_1361_amd/csrc/sweep_common.h", "paper_1206_1361_amd/csrc/gp_internal.h"]
 KERNEL_SOURCES = {
-    "nu_x": "paper_1206_1361_amd/csrc/sweep_x.hip",
-    "y": "paper_1206_1361_amd/csrc/sweep_yz.hip",
-    "z": "paper_1206_1361_amd/csrc/sweep_yz.hip",
+    "nu_x": ["paper_1206_1361_amd/csrc/sweep_x.hip", *_COMMON],
+    "y": ["paper_1206_1361_amd/csrc/sweep_yz.hip", *_COMMON],
+    "z": ["paper_1206_1361_amd/csrc/sweep_yz.hip", *_COMMON],
 }
 TRAFFIC_FILE = ROOT / "profiles" / "pmc_traffic.json"
 
@@ -49,8 +49,11 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_digest(path: str) -> str:
-    return hashlib.sha256((ROOT / path).read_bytes()).hexdigest()[:16]
+def source_digest(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        h.update((ROOT / p).read_bytes())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, dtype: str):
@@ -162,6 +165,9 @@ def main() -> int:
     ap.add_argument("--latency-repeats", type=int, default=50)
     ap.add_argument("--only", choices=["c128", "c64", "c64_f64"], default=None,
                     help="run one dtype only (profiling runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-MiB buffer three times with torch (a plain copy kernel "
+                         "of known size, to scale hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -178,6 +184,15 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     gp.lib()
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.calibrate_copy} MiB three times")
+        del src, dst
     w = inputs.LARGE_REAL
     log(f"[bench] generating the {w.name} initial state")
     psi_host = inputs.initial_state(w)

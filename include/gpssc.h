@@ -178,26 +178,24 @@ gp_status gp_profile_read(gp_plan *plan, double *ms, int64_t *launches);
  * (64 for x).  Host only.  GP_ERR_UNSUPPORTED if the line is too long. */
 gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *lanes);
 
-/* Host-only view of the constant sweep coefficients of one axis (no device
- * call), for inspection and tests.  For a line of n points, spacing dx,
- * step dt, mode and a chunking with chunk * lanes >= n, lanes <= 64, fills
- * (every complex value as an (re, im) pair of doubles):
- *   m[2*chunk*lanes]    Thomas pivots m_0 = 1/b, m_i = 1/(b - o^2 m_{i-1}),
- *                       zero past the end of the line, position-major;
- *   chunkprod[2*lanes]  product of a_i = -o m_i over each chunk;
- *   scan[2*2*6*lanes]   Kogge-Stone multipliers [direction][stage][lane]:
- *                       forward stage s, lane q = product of chunkprod over
- *                       q-2^s+1 .. q (0 if q < 2^s); backward = product over
- *                       q .. q+2^s-1 (0 if q+2^s >= lanes);
- *   coef[8]             b = 1 + kappa, o = -kappa/2 (left operator),
- *                       1 - kappa, kappa/2 (right operator), with
- *                       kappa = tau / (2 dx^2), tau = dt or i dt.
+/* Host-only view of the constant coefficients the sweep kernels use along
+ * one axis (no device call), for inspection and tests.  For a line of n
+ * points, spacing dx, step dt, mode and a chunking with chunk * lanes >= n,
+ * lanes <= 64.  With kappa = tau/(2 dx^2) (tau = dt or i dt) the
+ * Crank-Nicolson matrix of the line is tridiag(o, b, o), b = 1 + kappa,
+ * o = -kappa/2; the kernels solve it through the factorisation
+ *     tridiag(o, b, o) = beta (I + c S)(I + c S^T) + beta c^2 e_0 e_0^T
+ * (S the down-shift, |c| < 1, beta = o/c): w_i = m r_i + a w_{i-1},
+ * y_i = w_i + a y_{i+1} (m = 1/beta, a = -c), then x_i = y_i + y_0 zt_i.
+ * Fills, every complex value as an (re, im) pair of doubles:
+ *   coef[14]          kappa, b, o, c, beta, m, a;
+ *   stage[2*6]        a^(chunk 2^s), s = 0..5 (Kogge-Stone multipliers);
+ *   zt[2*n]           the boundary correction by position.
  * Lengths are counts of doubles.  GP_ERR_INVALID for bad arguments or short
  * buffers. */
 gp_status gp_sweep_tables(int64_t n, double dx, double dt, gp_mode mode, int chunk,
-                          int lanes, double *m, size_t m_len, double *chunkprod,
-                          size_t chunkprod_len, double *scan, size_t scan_len,
-                          double *coef, size_t coef_len);
+                          int lanes, double *coef, size_t coef_len, double *stage,
+                          size_t stage_len, double *zt, size_t zt_len);
 
 #ifdef __cplusplus
 }

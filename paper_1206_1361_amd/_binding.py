@@ -114,7 +114,7 @@ def lib() -> ctypes.CDLL:
     L.gp_profile_read.argtypes = [vp, dp, i64p]
     L.gp_sweep_shape.argtypes = [i64, ctypes.c_int, ctypes.c_int, ip, ip]
     L.gp_sweep_tables.argtypes = [i64, dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                  dp, sz, dp, sz, dp, sz, dp, sz]
+                                  dp, sz, dp, sz, dp, sz]
     for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_stream", "gp_step",
                  "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
                  "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables"):
@@ -165,23 +165,21 @@ def sweep_shape(n: int, axis: int, dtype="c128") -> tuple[int, int]:
 
 
 def sweep_tables(n: int, dx: float, dt: float, mode, chunk: int, lanes: int) -> dict:
-    """Host-only copy of the sweep coefficients (see gp_sweep_tables)."""
+    """Host-only copy of the constant sweep coefficients (see gp_sweep_tables)."""
     import numpy as np
 
-    npad = chunk * lanes
-    m = np.zeros(2 * npad)
-    cp = np.zeros(2 * lanes)
-    sc = np.zeros(2 * 2 * 6 * lanes)
-    coef = np.zeros(8)
+    coef = np.zeros(14)
+    stage = np.zeros(12)
+    zt = np.zeros(2 * n)
     dp = ctypes.POINTER(ctypes.c_double)
     _check(lib().gp_sweep_tables(int(n), float(dx), float(dt), _mode(mode), int(chunk), int(lanes),
-                                 m.ctypes.data_as(dp), m.size, cp.ctypes.data_as(dp), cp.size,
-                                 sc.ctypes.data_as(dp), sc.size, coef.ctypes.data_as(dp), coef.size),
+                                 coef.ctypes.data_as(dp), coef.size, stage.ctypes.data_as(dp), stage.size,
+                                 zt.ctypes.data_as(dp), zt.size),
            "gp_sweep_tables")
     c = lambda a: a[0::2] + 1j * a[1::2]  # noqa: E731
-    coefc = c(coef)
-    return {"m": c(m), "chunkprod": c(cp), "scan": c(sc).reshape(2, 6, lanes),
-            "b": coefc[0], "o": coefc[1], "rdiag": coefc[2], "roff": coefc[3]}
+    k = c(coef)
+    return {"kappa": k[0], "b": k[1], "o": k[2], "c": k[3], "beta": k[4], "m": k[5], "a": k[6],
+            "stage": c(stage), "zt": c(zt)}
 
 
 class Plan:

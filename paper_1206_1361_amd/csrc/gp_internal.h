@@ -63,17 +63,34 @@ __device__ __forceinline__ S st(cx<A> v)
     return r;
 }
 
+// Constant-coefficient factorisation of one axis.  The Crank-Nicolson
+// matrix tridiag(o, b, o) (b = 1 + kappa, o = -kappa/2) is Toeplitz, so with
+// c the root of o c^2 - b c + o = 0 inside the unit circle and beta = o / c,
+//     A = beta (I + c S)(I + c S^T) + beta c^2 e_0 e_0^T
+// (S the down-shift).  Solving (I + c S) w = m r (m = 1/beta), then
+// (I + c S^T) y = w, gives y = M^-1 r for M = beta (I + c S)(I + c S^T); the
+// rank-one term is restored by Sherman-Morrison: x = y + y_0 zt with
+// zt = -beta c^2 M^-1 e_0 / (1 + beta c^2 (M^-1 e_0)_0), which decays like c^i
+// from the first node.  Both recurrences have the single coefficient a = -c.
+template <typename A>
+struct SweepCoef {
+    A kap;                     // |kappa| = dt/(2 dx^2): kappa = kap (imag) or i kap (real time)
+    cx<A> m;                   // 1/beta
+    cx<A> a;                   // -c
+    cx<A> stage[kMaxStages];   // a^(chunk 2^s): Kogge-Stone stage multipliers
+    int nst;                   // stages with a nonzero multiplier
+    int nzc;                   // zt is nonzero only at positions < nzc
+};
+
 // Launch arguments of the calcnu + calclux kernel.
 template <typename A>
 struct XArgs {
     int nx, ny, nz;
-    int nst_f, nst_b;    // Kogge-Stone stages whose multipliers are not all zero
     A c0x, c0y, c0z;     // (N-1)/2 per axis: node i sits at (i - c0) * d
     A dx, dy, dz;
     A hgx, hgy, hgz;     // gamma^2/2, nu^2/2, lambda^2/2
     A dt, g;
-    cx<A> o;             // off-diagonal of (1 + tau/2 T): -kappa/2
-    cx<A> rd, ro;        // (1 - tau/2 T): diagonal 1 - kappa, off-diagonal kappa/2
+    SweepCoef<A> k;
 };
 
 // Launch arguments of the strided (y or z) sweep kernel.
@@ -82,10 +99,9 @@ struct SArgs {
     int nx;                // columns across a block (x extent)
     int n;                 // line length
     int lanes;             // chunks per line (blockDim.y)
-    int nst_f, nst_b;
     int64_t stride;        // element stride along the line
     int64_t outer_stride;  // element stride per blockIdx.y
-    cx<A> o, rd, ro;
+    SweepCoef<A> k;
 };
 
 // Sums of the observables pass, FP64.
@@ -110,18 +126,20 @@ struct ObsArgs {
 // float2/float, float2/double).
 enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2 };
 
-// calcnu + calclux.  m: [chunk][64] Thomas pivots; scan: [2][kMaxStages][64]
-// stage multipliers (forward, backward).  scale: NULL or device double.
+// calcnu + calclux.  zt: boundary correction by position (complex, the
+// arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
+// nblocks: resident one-wavefront blocks to launch (each loops over lines).
+hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
+                       const void *zt, const double *scale, hipStream_t stream);
 
-hipError_t launch_nu_x(Prec prec, bool real, int chunk, void *psi, const void *args,
-                       const void *m, const void *scan, const double *scale,
-                       hipStream_t stream);
+// Blocks of the x kernel that fit on the device at once (all compute units).
+int nu_x_resident_blocks(Prec prec, bool real, int chunk);
 
-// calcluy / calcluz.  m: [lanes*chunk] pivots; scan: [2][kMaxStages][lanes].
-// partials: NULL, or one double per block (sum |psi|^2 of the block's output).
-hipError_t launch_strided(Prec prec, int chunk, int xt, int nouter, void *psi,
-                          const void *args, const void *m, const void *scan,
-                          double *partials, hipStream_t stream);
+// calcluy / calcluz.  zt: boundary correction by position.  partials: NULL,
+// or one double per block (sum |psi|^2 of the block's output).
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, void *psi,
+                          const void *args, const void *zt, double *partials,
+                          hipStream_t stream);
 
 // calcnorm: sums `n` partials in a fixed order, writes 1/sqrt(dv*sum) to
 // *scale and raises *flag if the norm is not finite and positive.

@@ -42,9 +42,15 @@ gp_status fail_hip(hipError_t e, const char *what)
 const int kChunksX[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
 const int kChunksYZ[] = {1, 2, 4, 8, 16};
 
+int max_lanes_for(gp_dtype dtype) { return dtype == GP_C64 ? 32 : gpssc::kMaxLanesYZ; }
+
 // Chunking of a line of n points along `axis`: chunk points per lane, lanes
 // per line.  Returns false when the line is longer than the kernels handle.
-bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes)
+// y/z: the fewest points per thread that keep the chunks of a line within
+// max_lanes; FP32 arithmetic affords 16-point chunks at 32 chunks per line
+// (fewer scan stages, wider blocks), FP64 keeps 64 chunks of at most 8
+// points for lines up to 512 so two 1024-thread blocks fit on a compute unit.
+bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes, int max_lanes = gpssc::kMaxLanesYZ)
 {
     if (n < 1) return false;
     if (axis == 0) {
@@ -58,7 +64,7 @@ bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes)
     }
     for (int c : kChunksYZ) {
         const int64_t p = (n + c - 1) / c;
-        if (p <= gpssc::kMaxLanesYZ) {
+        if (p <= max_lanes || (c == kChunksYZ[4] && p <= gpssc::kMaxLanesYZ)) {
             *chunk = c;
             *lanes = (int)p;
             return true;
@@ -70,120 +76,114 @@ bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes)
 // Columns per y/z block: as wide as 64 (one full wavefront of contiguous
 // x), narrowed so the block holds at most 1024 threads and not far wider
 // than the grid.
+#ifndef GPSSC_YZ_COLS
+#define GPSSC_YZ_COLS 64
+#endif
 int strided_columns(int64_t nx, int lanes)
 {
-    int xt = 64;
+    int xt = GPSSC_YZ_COLS;
     while (xt * lanes > gpssc::kMaxBlockYZ) xt /= 2;
     while (xt > 16 && xt / 2 >= nx) xt /= 2;
     return xt;
 }
 
-// Constant tables of one axis, FP64.
+// Constant coefficients of one axis, FP64.  Crank-Nicolson along the axis:
+// (1 + tau/2 T) psi' = (1 - tau/2 T) psi, T psi_i = -(psi_{i+1} - 2 psi_i +
+// psi_{i-1})/(2 dx^2), tau = dt or i dt.  With kappa = tau/(2 dx^2) the left
+// matrix is tridiag(o, b, o), b = 1 + kappa, o = -kappa/2, and the right side
+// is (1 - kappa) psi_i + kappa/2 (psi_{i-1} + psi_{i+1}).
 struct AxisTables {
     int64_t n = 0;
     int chunk = 0, lanes = 0;
-    cplx b, o, rd, ro;               // left diagonal / off-diagonal, right diagonal / off-diagonal
-    std::vector<cplx> m;             // Thomas pivots, position-major, chunk*lanes, zero past n
-    std::vector<cplx> chunkprod;     // product of a_i = -o m_i over each chunk
-    std::vector<cplx> scan;          // [2][kMaxStages][lanes]: forward, backward stage multipliers
+    cplx kappa, b, o;
+    cplx c, beta, m, a;          // A = beta (I + c S)(I + c S^T) + beta c^2 e0 e0^T; m = 1/beta, a = -c
+    std::vector<cplx> zt;        // boundary correction x = y + y_0 zt, by position
+    cplx stage[gpssc::kMaxStages];  // a^(chunk 2^s)
 };
 
-// Crank-Nicolson along one axis: (1 + tau/2 T) psi' = (1 - tau/2 T) psi with
-// T psi_i = -(psi_{i+1} - 2 psi_i + psi_{i-1})/(2 dx^2) and tau = dt or i dt.
-// With kappa = tau/(2 dx^2): left  b = 1 + kappa, o = -kappa/2;
-//                            right 1 - kappa and kappa/2.
-// Thomas pivots m_0 = 1/b, m_i = 1/(b - o c'_{i-1}), c'_i = o m_i.
+// The factorisation: c is the root of o c^2 - b c + o = 0 inside the unit
+// circle (the two roots multiply to 1), taken as 2o / (b + sqrt(b^2 - 4o^2))
+// with the square root that makes |c| < 1, so nothing cancels.  beta = o/c,
+// so beta (1 + c^2) = b and beta c = o.
 void build_axis(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t)
 {
     const cplx tau = real ? cplx(0.0, dt) : cplx(dt, 0.0);
-    const cplx kappa = tau / (2.0 * dx * dx);
     t.n = n;
     t.chunk = chunk;
     t.lanes = lanes;
-    t.b = 1.0 + kappa;
-    t.o = -0.5 * kappa;
-    t.rd = 1.0 - kappa;
-    t.ro = 0.5 * kappa;
-    const int64_t npad = (int64_t)chunk * lanes;
-    t.m.assign((size_t)npad, cplx(0.0, 0.0));
-    cplx cprev(0.0, 0.0);
-    for (int64_t i = 0; i < n; ++i) {
-        t.m[(size_t)i] = 1.0 / (t.b - t.o * cprev);
-        cprev = t.o * t.m[(size_t)i];
-    }
-    t.chunkprod.assign((size_t)lanes, cplx(1.0, 0.0));
-    for (int q = 0; q < lanes; ++q)
-        for (int c = 0; c < chunk; ++c)
-            t.chunkprod[(size_t)q] *= -t.o * t.m[(size_t)q * chunk + c];
-    // Kogge-Stone multipliers.  Forward, stage s, lane q: product of the
-    // chunk products q-2^s+1 .. q (lane q adds lane q-2^s's partial).
-    // Backward: product of q .. q+2^s-1 (lane q adds lane q+2^s's partial).
-    t.scan.assign((size_t)2 * gpssc::kMaxStages * lanes, cplx(0.0, 0.0));
+    t.kappa = tau / (2.0 * dx * dx);
+    t.b = 1.0 + t.kappa;
+    t.o = -0.5 * t.kappa;
+    const cplx disc = std::sqrt(t.b * t.b - 4.0 * t.o * t.o);
+    const cplx den = std::abs(t.b + disc) >= std::abs(t.b - disc) ? t.b + disc : t.b - disc;
+    t.c = 2.0 * t.o / den;
+    t.beta = t.o / t.c;
+    t.m = 1.0 / t.beta;
+    t.a = -t.c;
+    // z = M^-1 e_0 for M = beta (I + c S)(I + c S^T): forward w_i = a^i / beta,
+    // then back substitution y_i = w_i + a y_{i+1} from the last node.
+    std::vector<cplx> w((size_t)n), z((size_t)n);
+    w[0] = t.m;
+    for (int64_t i = 1; i < n; ++i) w[(size_t)i] = t.a * w[(size_t)i - 1];
+    z[(size_t)n - 1] = w[(size_t)n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) z[(size_t)i] = w[(size_t)i] + t.a * z[(size_t)i + 1];
+    // A = M + u e_0^T, u = beta c^2 e_0:  x = y - (beta c^2 y_0 / (1 + beta c^2 z_0)) z
+    const cplx bc2 = t.beta * t.c * t.c;
+    const cplx gam = -bc2 / (1.0 + bc2 * z[0]);
+    t.zt.resize((size_t)n);
+    for (int64_t i = 0; i < n; ++i) t.zt[(size_t)i] = gam * z[(size_t)i];
+    cplx p(1.0, 0.0);
+    for (int q = 0; q < chunk; ++q) p *= t.a;
     for (int s = 0; s < gpssc::kMaxStages; ++s) {
-        const int d = 1 << s;
-        for (int q = 0; q < lanes; ++q) {
-            if (q - d >= 0) {
-                cplx p(1.0, 0.0);
-                for (int l = q - d + 1; l <= q; ++l) p *= t.chunkprod[(size_t)l];
-                t.scan[(size_t)s * lanes + q] = p;
-            }
-            if (q + d <= lanes - 1) {
-                cplx p(1.0, 0.0);
-                for (int l = q; l <= q + d - 1; ++l) p *= t.chunkprod[(size_t)l];
-                t.scan[(size_t)(gpssc::kMaxStages + s) * lanes + q] = p;
-            }
-        }
-    }
-}
-
-// Stages with a nonzero multiplier once rounded to the arithmetic type;
-// every later stage is all zero too (its multipliers are products of the
-// earlier ones), so skipping it changes nothing.
-template <typename A>
-void count_stages(const AxisTables &t, int *nst_f, int *nst_b)
-{
-    *nst_f = 0;
-    *nst_b = 0;
-    for (int s = 0; s < gpssc::kMaxStages; ++s) {
-        if ((1 << s) >= t.lanes) break;
-        bool fnz = false, bnz = false;
-        for (int q = 0; q < t.lanes; ++q) {
-            const cplx f = t.scan[(size_t)s * t.lanes + q];
-            const cplx b = t.scan[(size_t)(gpssc::kMaxStages + s) * t.lanes + q];
-            if ((A)f.real() != (A)0 || (A)f.imag() != (A)0) fnz = true;
-            if ((A)b.real() != (A)0 || (A)b.imag() != (A)0) bnz = true;
-        }
-        if (fnz) *nst_f = s + 1;
-        if (bnz) *nst_b = s + 1;
+        t.stage[s] = p;
+        p *= p;
     }
 }
 
 template <typename A>
 cx<A> to_cx(cplx v) { return cx<A>{(A)v.real(), (A)v.imag()}; }
 
-// Device image of the tables of the three axes, in the arithmetic type.
-// x pivots are stored [chunk][64] so the per-lane reads coalesce; y/z pivots
-// position-major (all lanes of a row of the block read the same entry).
 template <typename A>
-std::vector<unsigned char> pack_tables(const AxisTables ax[3], size_t off[6])
+bool is_zero(cplx v) { return (A)v.real() == (A)0 && (A)v.imag() == (A)0; }
+
+// Coefficients of one axis in the arithmetic type.  Stages whose multiplier
+// rounds to zero are dropped (every later one is zero too: it is the square
+// of the previous); stages that would reach past the last lane are dropped
+// because no lane has a partner there.  The correction is kept up to its last
+// position that does not round to zero.
+template <typename A>
+gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, double dt, double dx)
+{
+    gpssc::SweepCoef<A> k;
+    k.kap = (A)(dt / (2.0 * dx * dx));
+    k.m = to_cx<A>(t.m);
+    k.a = to_cx<A>(t.a);
+    k.nst = 0;
+    for (int s = 0; s < gpssc::kMaxStages; ++s) {
+        k.stage[s] = to_cx<A>(t.stage[s]);
+        if ((1 << s) < t.lanes && !is_zero<A>(t.stage[s]) && k.nst == s) k.nst = s + 1;
+    }
+    int nz = (int)t.n;
+    while (nz > 0 && is_zero<A>(t.zt[(size_t)nz - 1])) --nz;
+    k.nzc = nz;
+    return k;
+}
+
+// Device image of the correction vectors of the three axes, in the
+// arithmetic type, each padded to chunk * lanes positions.
+template <typename A>
+std::vector<unsigned char> pack_tables(const AxisTables ax[3], size_t off[3])
 {
     std::vector<cx<A>> v;
-    // x pivots
-    off[0] = v.size();
-    for (int c = 0; c < ax[0].chunk; ++c)
-        for (int l = 0; l < gpssc::kWave; ++l)
-            v.push_back(to_cx<A>(ax[0].m[(size_t)l * ax[0].chunk + c]));
-    off[1] = v.size();
-    for (const cplx &s : ax[0].scan) v.push_back(to_cx<A>(s));
-    for (int a = 1; a < 3; ++a) {
-        off[2 * a] = v.size();
-        for (const cplx &m : ax[a].m) v.push_back(to_cx<A>(m));
-        off[2 * a + 1] = v.size();
-        for (const cplx &s : ax[a].scan) v.push_back(to_cx<A>(s));
+    for (int a = 0; a < 3; ++a) {
+        off[a] = v.size();
+        for (const cplx &z : ax[a].zt) v.push_back(to_cx<A>(z));
+        const size_t npad = (size_t)ax[a].chunk * ax[a].lanes;
+        while (v.size() - off[a] < npad) v.push_back(cx<A>{0, 0});
     }
     std::vector<unsigned char> bytes(v.size() * sizeof(cx<A>));
     std::memcpy(bytes.data(), v.data(), bytes.size());
-    for (int q = 0; q < 6; ++q) off[q] *= sizeof(cx<A>);
+    for (int q = 0; q < 3; ++q) off[q] *= sizeof(cx<A>);
     return bytes;
 }
 
@@ -234,10 +234,10 @@ struct gp_plan {
 
     AxisTables ax[3];
     int xt_y, xt_z;
-    int nst_f[3], nst_b[3];
+    int x_blocks;   // resident blocks of the persistent x kernel
 
     unsigned char *d_tables = nullptr;
-    size_t tab_off[6];
+    size_t tab_off[3];
     double *d_partials = nullptr;   // z-sweep norm partials
     int n_zblocks = 0;
     double *d_obs_partials = nullptr;
@@ -267,8 +267,6 @@ void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
     x.nx = (int)p->n[0];
     x.ny = (int)p->n[1];
     x.nz = (int)p->n[2];
-    x.nst_f = p->nst_f[0];
-    x.nst_b = p->nst_b[0];
     x.c0x = (A)(0.5 * (double)(p->n[0] - 1));
     x.c0y = (A)(0.5 * (double)(p->n[1] - 1));
     x.c0z = (A)(0.5 * (double)(p->n[2] - 1));
@@ -280,21 +278,15 @@ void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
     x.hgz = (A)(0.5 * p->omega[2] * p->omega[2]);
     x.dt = (A)p->dt;
     x.g = (A)p->g;
-    x.o = to_cx<A>(p->ax[0].o);
-    x.rd = to_cx<A>(p->ax[0].rd);
-    x.ro = to_cx<A>(p->ax[0].ro);
+    x.k = sweep_coef<A>(p->ax[0], p->dt, p->dx[0]);
     for (int a = 1; a < 3; ++a) {
         gpssc::SArgs<A> &t = s[a - 1];
         t.nx = (int)p->n[0];
         t.n = (int)p->n[a];
         t.lanes = p->ax[a].lanes;
-        t.nst_f = p->nst_f[a];
-        t.nst_b = p->nst_b[a];
         t.stride = a == 1 ? p->n[0] : p->n[0] * p->n[1];
         t.outer_stride = a == 1 ? p->n[0] * p->n[1] : p->n[0];
-        t.o = to_cx<A>(p->ax[a].o);
-        t.rd = to_cx<A>(p->ax[a].rd);
-        t.ro = to_cx<A>(p->ax[a].ro);
+        t.k = sweep_coef<A>(p->ax[a], p->dt, p->dx[a]);
     }
 }
 
@@ -328,10 +320,10 @@ size_t footprint(const int64_t grid[3], gp_dtype dtype, int *xt_y, int *xt_z)
 {
     int c[3], l[3];
     for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &c[a], &l[a])) return 0;
+        if (!sweep_shape(grid[a], a, &c[a], &l[a], max_lanes_for(dtype))) return 0;
     const size_t cs = dtype == GP_C64 ? 8 : 16;   // table entries: complex<float> or <double>
-    size_t tab = (size_t)c[0] * gpssc::kWave + 2 * gpssc::kMaxStages * gpssc::kWave;
-    for (int a = 1; a < 3; ++a) tab += (size_t)c[a] * l[a] + 2 * gpssc::kMaxStages * l[a];
+    size_t tab = 0;
+    for (int a = 0; a < 3; ++a) tab += (size_t)c[a] * l[a];
     tab *= cs;
     const int xy = strided_columns(grid[0], l[1]);
     const int xz = strided_columns(grid[0], l[2]);
@@ -421,39 +413,34 @@ gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *l
     if (!chunk || !lanes || axis < 0 || axis > 2 || !valid_dtype(dtype))
         return fail(GP_ERR_INVALID, "bad gp_sweep_shape arguments");
     if (n < 1) return fail(GP_ERR_INVALID, "line length must be >= 1");
-    if (!sweep_shape(n, axis, chunk, lanes)) return fail(GP_ERR_UNSUPPORTED, "line too long");
+    if (!sweep_shape(n, axis, chunk, lanes, max_lanes_for(dtype))) return fail(GP_ERR_UNSUPPORTED, "line too long");
     return GP_OK;
 }
 
 gp_status gp_sweep_tables(int64_t n, double dx, double dt, gp_mode mode, int chunk, int lanes,
-                          double *m, size_t m_len, double *chunkprod, size_t chunkprod_len,
-                          double *scan, size_t scan_len, double *coef, size_t coef_len)
+                          double *coef, size_t coef_len, double *stage, size_t stage_len,
+                          double *zt, size_t zt_len)
 {
     if (n < 1 || !finite_pos(dx) || !finite_pos(dt) || (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) ||
         chunk < 1 || lanes < 1 || (int64_t)chunk * lanes < n || lanes > gpssc::kWave)
         return fail(GP_ERR_INVALID, "bad gp_sweep_tables arguments");
-    const size_t npad = (size_t)chunk * lanes;
-    if (!m || m_len < 2 * npad || !chunkprod || chunkprod_len < 2 * (size_t)lanes || !scan ||
-        scan_len < 2 * 2 * (size_t)gpssc::kMaxStages * lanes || !coef || coef_len < 8)
+    if (!coef || coef_len < 14 || !stage || stage_len < 2 * (size_t)gpssc::kMaxStages || !zt ||
+        zt_len < 2 * (size_t)n)
         return fail(GP_ERR_INVALID, "gp_sweep_tables output buffer too short");
     AxisTables t;
     build_axis(n, dx, dt, mode == GP_MODE_REAL, chunk, lanes, t);
-    for (size_t i = 0; i < npad; ++i) {
-        m[2 * i] = t.m[i].real();
-        m[2 * i + 1] = t.m[i].imag();
+    const cplx c7[7] = {t.kappa, t.b, t.o, t.c, t.beta, t.m, t.a};
+    for (int q = 0; q < 7; ++q) {
+        coef[2 * q] = c7[q].real();
+        coef[2 * q + 1] = c7[q].imag();
     }
-    for (int q = 0; q < lanes; ++q) {
-        chunkprod[2 * q] = t.chunkprod[(size_t)q].real();
-        chunkprod[2 * q + 1] = t.chunkprod[(size_t)q].imag();
+    for (int s = 0; s < gpssc::kMaxStages; ++s) {
+        stage[2 * s] = t.stage[s].real();
+        stage[2 * s + 1] = t.stage[s].imag();
     }
-    for (size_t i = 0; i < t.scan.size(); ++i) {
-        scan[2 * i] = t.scan[i].real();
-        scan[2 * i + 1] = t.scan[i].imag();
-    }
-    const cplx c4[4] = {t.b, t.o, t.rd, t.ro};
-    for (int q = 0; q < 4; ++q) {
-        coef[2 * q] = c4[q].real();
-        coef[2 * q + 1] = c4[q].imag();
+    for (int64_t i = 0; i < n; ++i) {
+        zt[2 * i] = t.zt[(size_t)i].real();
+        zt[2 * i + 1] = t.zt[(size_t)i].imag();
     }
     return GP_OK;
 }
@@ -482,7 +469,7 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
     int chunk[3], lanes[3];
     for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a]))
+        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a], max_lanes_for(dtype)))
             return fail(GP_ERR_UNSUPPORTED, "grid line too long (Nx <= 1024, Ny, Nz <= 1024)");
     if (grid[1] * grid[2] > 0x7fffffffLL || grid[1] > 65535 || grid[2] > 65535)
         return fail(GP_ERR_UNSUPPORTED, "too many grid lines for one launch");
@@ -507,12 +494,6 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
 
     const bool real = mode == GP_MODE_REAL;
     for (int a = 0; a < 3; ++a) build_axis(grid[a], dx[a], dt, real, chunk[a], lanes[a], p->ax[a]);
-    for (int a = 0; a < 3; ++a) {
-        if (dtype == GP_C64)
-            count_stages<float>(p->ax[a], &p->nst_f[a], &p->nst_b[a]);
-        else
-            count_stages<double>(p->ax[a], &p->nst_f[a], &p->nst_b[a]);
-    }
     footprint(grid, dtype, &p->xt_y, &p->xt_z);
     std::vector<unsigned char> tab = dtype == GP_C64 ? pack_tables<float>(p->ax, p->tab_off)
                                                      : pack_tables<double>(p->ax, p->tab_off);
@@ -552,6 +533,12 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     }
     fill_args<double>(p, p->xd, p->sd);
     fill_args<float>(p, p->xf, p->sf);
+    p->x_blocks = gpssc::nu_x_resident_blocks(static_cast<gpssc::Prec>(dtype), real, chunk[0]);
+    if (p->x_blocks <= 0) {
+        (void)hipGetLastError();
+        release(p);
+        return fail(GP_ERR_DEVICE, "querying the occupancy of the x kernel failed");
+    }
     *out = p;
     return GP_OK;
 }
@@ -605,19 +592,19 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps)
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
         const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
         e = timed(p, GP_KERNEL_NU_X, [&] {
-            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, psi, xargs, T + p->tab_off[0],
-                                      T + p->tab_off[1], scale, p->stream);
+            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
+                                      T + p->tab_off[0], scale, p->stream);
         });
         if (e != hipSuccess) break;
         e = timed(p, GP_KERNEL_Y, [&] {
-            return gpssc::launch_strided(prec, p->ax[1].chunk, p->xt_y, (int)p->n[2], psi, yargs,
-                                         T + p->tab_off[2], T + p->tab_off[3], nullptr, p->stream);
+            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2], psi,
+                                         yargs, T + p->tab_off[1], nullptr, p->stream);
         });
         if (e != hipSuccess) break;
         e = timed(p, GP_KERNEL_Z, [&] {
-            return gpssc::launch_strided(prec, p->ax[2].chunk, p->xt_z, (int)p->n[1], psi, zargs,
-                                         T + p->tab_off[4], T + p->tab_off[5],
-                                         real ? nullptr : p->d_partials, p->stream);
+            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1], psi,
+                                         zargs, T + p->tab_off[2], real ? nullptr : p->d_partials,
+                                         p->stream);
         });
         if (e != hipSuccess || real) continue;
         e = timed(p, GP_KERNEL_NORM, [&] {
@@ -711,14 +698,23 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
 gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
 {
     if (!p || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_plan_describe arguments");
+    const bool a32 = p->dtype == GP_C64;
+    int nst[3], nzc[3];
+    const gpssc::SweepCoef<double> *kd[3] = {&p->xd.k, &p->sd[0].k, &p->sd[1].k};
+    const gpssc::SweepCoef<float> *kf[3] = {&p->xf.k, &p->sf[0].k, &p->sf[1].k};
+    for (int a = 0; a < 3; ++a) {
+        nst[a] = a32 ? kf[a]->nst : kd[a]->nst;
+        nzc[a] = a32 ? kf[a]->nzc : kd[a]->nzc;
+    }
+    const char *dt = p->dtype == GP_C64 ? "c64" : (p->dtype == GP_C64_F64 ? "c64/f64" : "c128");
     std::snprintf(buf, len,
-                  "grid %lldx%lldx%lld %s %s | x: chunk %d, 64 lanes, stages %d/%d | "
-                  "y: chunk %d, %d lanes, %d cols, stages %d/%d | z: chunk %d, %d lanes, %d cols, stages %d/%d",
+                  "grid %lldx%lldx%lld %s %s | x: chunk %d x 64 lanes, %d stages, correction %d | "
+                  "y: chunk %d x %d lanes, %d cols, %d stages, correction %d | "
+                  "z: chunk %d x %d lanes, %d cols, %d stages, correction %d",
                   (long long)p->n[0], (long long)p->n[1], (long long)p->n[2],
-                  p->mode == GP_MODE_REAL ? "real" : "imag", p->dtype == GP_C64 ? "c64" : (p->dtype == GP_C64_F64 ? "c64/f64" : "c128"),
-                  p->ax[0].chunk, p->nst_f[0], p->nst_b[0], p->ax[1].chunk, p->ax[1].lanes, p->xt_y,
-                  p->nst_f[1], p->nst_b[1], p->ax[2].chunk, p->ax[2].lanes, p->xt_z, p->nst_f[2],
-                  p->nst_b[2]);
+                  p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
+                  p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->ax[2].chunk,
+                  p->ax[2].lanes, p->xt_z, nst[2], nzc[2]);
     return GP_OK;
 }
 

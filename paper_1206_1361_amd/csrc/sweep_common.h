@@ -1,0 +1,172 @@
+// sweep_common.h -- pieces shared by the x and the y/z Crank-Nicolson sweep
+// kernels: the right-hand side, the passes of the constant-coefficient
+// factorisation over a chunk, and the phase factor of calcnu.  Internal to
+// libgpssc.
+#pragma once
+
+#include "gp_internal.h"
+
+namespace gpssc {
+
+// coef * v for a Crank-Nicolson coefficient.  In imaginary time every
+// coefficient is real (tau = dt), so only the real part is used.
+template <bool REAL, typename A>
+__device__ __forceinline__ cx<A> kmul(cx<A> coef, cx<A> v)
+{
+    if (REAL) return cmul(coef, v);
+    return cx<A>{coef.re * v.re, coef.re * v.im};
+}
+
+// coef * t + v
+template <bool REAL, typename A>
+__device__ __forceinline__ cx<A> kfma(cx<A> coef, cx<A> t, cx<A> v)
+{
+    if (REAL) return cfma(coef, t, v);
+    return cx<A>{fma(coef.re, t.re, v.re), fma(coef.re, t.im, v.im)};
+}
+
+// Right-hand side (1 - tau/2 T) psi at one point from its neighbours:
+//   (1 - kappa) u + kappa/2 (lo + hi) = u + kappa w,  w = (lo + hi)/2 - u,
+// with kappa = dt/(2 dx^2) (imaginary time) or i dt/(2 dx^2) (real time).
+template <bool REAL, typename A>
+__device__ __forceinline__ cx<A> cn_rhs(A kap, cx<A> lo, cx<A> u, cx<A> hi)
+{
+    const cx<A> w = cx<A>{fma((A)0.5, lo.re + hi.re, -u.re), fma((A)0.5, lo.im + hi.im, -u.im)};
+    if (REAL) return cx<A>{fma(-kap, w.im, u.re), fma(kap, w.re, u.im)};
+    return cx<A>{fma(kap, w.re, u.re), fma(kap, w.im, u.im)};
+}
+
+// Passes over one chunk of C points held in registers.  The coefficients
+// are the same at every position (SweepCoef), so they live in scalar
+// registers.
+
+// u <- m (1 - tau/2 T) u, with the points either side of the chunk.
+template <bool REAL, int C, typename A>
+__device__ __forceinline__ void chunk_rhs(cx<A> (&u)[C], cx<A> left, cx<A> right,
+                                          const SweepCoef<A> &k)
+{
+    cx<A> prev = left;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const cx<A> cur = u[c];
+        const cx<A> rhs = cn_rhs<REAL>(k.kap, prev, cur, c < C - 1 ? u[c + 1] : right);
+        prev = cur;
+        u[c] = kmul<REAL>(k.m, rhs);
+    }
+}
+
+// Forward recurrence t <- u_c + a t from carry t; returns the last value
+// and, if STORE, leaves every value in u.
+template <bool REAL, bool STORE, int C, typename A>
+__device__ __forceinline__ cx<A> chunk_forward(cx<A> (&u)[C], cx<A> t, const SweepCoef<A> &k)
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        t = kfma<REAL>(k.a, t, u[c]);
+        if (STORE) u[c] = t;
+    }
+    return t;
+}
+
+// Backward recurrence t <- u_c + a t from the chunk end.
+template <bool REAL, bool STORE, int C, typename A>
+__device__ __forceinline__ cx<A> chunk_backward(cx<A> (&u)[C], cx<A> t, const SweepCoef<A> &k)
+{
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        t = kfma<REAL>(k.a, t, u[c]);
+        if (STORE) u[c] = t;
+    }
+    return t;
+}
+
+// Zero the values at positions >= n (the padding after the end of a line),
+// so nothing past the last node feeds the back substitution.
+template <int C, typename A>
+__device__ __forceinline__ void chunk_clear_padding(cx<A> (&u)[C], int pos0, int n)
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (pos0 + c >= n) u[c] = cx<A>{0, 0};
+}
+
+// Boundary correction x_i = y_i + y_0 zt_i for positions < nzc.
+template <bool REAL, int C, typename A>
+__device__ __forceinline__ void chunk_correct(cx<A> (&u)[C], cx<A> y0, const cx<A> *__restrict__ zt,
+                                              int pos0, int nzc)
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        if (pos0 + c < nzc) u[c] = kfma<REAL>(zt[pos0 + c], y0, u[c]);
+}
+
+// The library sin/cos for phases beyond pi/4, kept out of line: the path is
+// rare (a phase that large per step means a very coarse time step), and
+// inlining it would raise the register count of the whole sweep.
+template <typename A> __device__ __attribute__((noinline)) void sincos_lib(A x, A *s, A *c);
+template <> __device__ __attribute__((noinline)) void sincos_lib<double>(double x, double *s, double *c) { sincos(x, s, c); }
+template <> __device__ __attribute__((noinline)) void sincos_lib<float>(float x, float *s, float *c) { sincosf(x, s, c); }
+template <typename A> __device__ __forceinline__ A exp_lib(A x);
+template <> __device__ __forceinline__ double exp_lib<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float exp_lib<float>(float x) { return expf(x); }
+
+// sin and cos for |x| <= pi/4 from their Taylor series, evaluated by
+// Horner's rule in z = x^2.  The first omitted terms, x^17/17! and x^18/18!
+// (FP64) or x^11/11! and x^12/12! (FP32), are below half an ulp of the
+// result on that interval.
+__device__ __forceinline__ void sincos_taylor(double x, double *s, double *c)
+{
+    const double z = x * x;
+    double ps = 1.0 / 1307674368000.0;                  // 1/15!
+    ps = fma(ps, -z, 1.0 / 6227020800.0);               // 1/13!
+    ps = fma(ps, -z, 1.0 / 39916800.0);                 // 1/11!
+    ps = fma(ps, -z, 1.0 / 362880.0);                   // 1/9!
+    ps = fma(ps, -z, 1.0 / 5040.0);                     // 1/7!
+    ps = fma(ps, -z, 1.0 / 120.0);                      // 1/5!
+    ps = fma(ps, -z, 1.0 / 6.0);                        // 1/3!
+    *s = fma(-x * z, ps, x);
+    double pc = 1.0 / 20922789888000.0;                 // 1/16!
+    pc = fma(pc, -z, 1.0 / 87178291200.0);              // 1/14!
+    pc = fma(pc, -z, 1.0 / 479001600.0);                // 1/12!
+    pc = fma(pc, -z, 1.0 / 3628800.0);                  // 1/10!
+    pc = fma(pc, -z, 1.0 / 40320.0);                    // 1/8!
+    pc = fma(pc, -z, 1.0 / 720.0);                      // 1/6!
+    pc = fma(pc, -z, 1.0 / 24.0);                       // 1/4!
+    pc = fma(pc, -z, 0.5);                              // 1/2!
+    *c = fma(-z, pc, 1.0);
+}
+
+__device__ __forceinline__ void sincos_taylor(float x, float *s, float *c)
+{
+    const float z = x * x;
+    float ps = 1.0f / 362880.0f;                        // 1/9!
+    ps = fmaf(ps, -z, 1.0f / 5040.0f);                  // 1/7!
+    ps = fmaf(ps, -z, 1.0f / 120.0f);                   // 1/5!
+    ps = fmaf(ps, -z, 1.0f / 6.0f);                     // 1/3!
+    *s = fmaf(-x * z, ps, x);
+    float pc = 1.0f / 3628800.0f;                       // 1/10!
+    pc = fmaf(pc, -z, 1.0f / 40320.0f);                 // 1/8!
+    pc = fmaf(pc, -z, 1.0f / 720.0f);                   // 1/6!
+    pc = fmaf(pc, -z, 1.0f / 24.0f);                    // 1/4!
+    pc = fmaf(pc, -z, 0.5f);                            // 1/2!
+    *c = fmaf(-z, pc, 1.0f);
+}
+
+// calcnu phase factor: v * exp(-i phi) (real time) or v * exp(-phi)
+// (imaginary time), phi = dt * (V + g|v|^2).
+template <bool REAL, typename A>
+__device__ __forceinline__ cx<A> nu_factor(cx<A> v, A phi)
+{
+    if (REAL) {
+        A sn, cs;
+        if (fabs(phi) <= (A)0.78539816339744830962)
+            sincos_taylor(phi, &sn, &cs);
+        else
+            sincos_lib<A>(phi, &sn, &cs);
+        return cx<A>{fma(v.re, cs, v.im * sn), fma(v.im, cs, -v.re * sn)};
+    }
+    const A f = exp_lib<A>(-phi);
+    return cx<A>{v.re * f, v.im * f};
+}
+
+}  // namespace gpssc

@@ -9,17 +9,18 @@
 // along x: a block covers XT neighbouring lines (one per threadIdx.x, so every
 // load and store of a row of the block is one contiguous segment) and cuts
 // each line into P = blockDim.y contiguous chunks of C points held in
-// registers.  Thomas runs per chunk with a zero carry; the carries between
-// chunks come from a Kogge-Stone scan through LDS whose stage multipliers are
-// precomputed on the host; each chunk then reruns from its true carry.
-#include "gp_internal.h"
+// registers.  The solve is the constant-coefficient factorisation of the x
+// kernel: per-chunk recurrences with a zero carry, the carries between chunks
+// from a Kogge-Stone scan through LDS, a rerun from the true carry, and the
+// rank-one boundary term from the first node.
+#include "sweep_common.h"
 
 namespace gpssc {
 
-template <typename S, typename A, int C, bool NORM>
+template <typename S, typename A, int C, bool REAL, bool NORM>
 __global__ void __launch_bounds__(kMaxBlockYZ)
-calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ mtab,
-                      const cx<A> *__restrict__ scan, double *__restrict__ partials)
+calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ zt,
+                      double *__restrict__ partials)
 {
     extern __shared__ unsigned char smem_raw[];
     const int XT = blockDim.x;
@@ -32,88 +33,83 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
 
     const int i = blockIdx.x * XT + tx;
     const bool act = i < a.nx;
-    S *base = psi + (int64_t)blockIdx.y * a.outer_stride + i;
+    const int pos0 = pc * C;
+    const bool full = act && pos0 + C <= a.n;   // whole chunk inside the line
+    S *base = psi + (int64_t)blockIdx.y * a.outer_stride + i + (int64_t)pos0 * a.stride;
 
     cx<A> u[C];
+    if (full) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int pos = pc * C + c;
-        u[c] = cx<A>{0, 0};
-        if (act && pos < a.n) u[c] = ld<A>(base[(int64_t)pos * a.stride]);
+        for (int c = 0; c < C; ++c) u[c] = ld<A>(base[(int64_t)c * a.stride]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            u[c] = cx<A>{0, 0};
+            if (act && pos0 + c < a.n) u[c] = ld<A>(base[(int64_t)c * a.stride]);
+        }
     }
 
     // neighbours across chunk borders
     b0[me] = u[0];
     b1[me] = u[C - 1];
     __syncthreads();
-    const cx<A> left = pc > 0 ? b1[me - XT] : cx<A>{0, 0};
-    const cx<A> right = pc < P - 1 ? b0[me + XT] : cx<A>{0, 0};
+    const cx<A> zero = cx<A>{0, 0};
+    const cx<A> left = pc > 0 ? b1[me - XT] : zero;
+    const cx<A> right = pc < P - 1 ? b0[me + XT] : zero;
+    chunk_rhs<REAL>(u, left, right, a.k);
 
-    cx<A> q[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const cx<A> lo = c > 0 ? u[c - 1] : left;
-        const cx<A> hi = c < C - 1 ? u[c + 1] : right;
-        q[c] = cfma(a.ro, cadd(lo, hi), cmul(a.rd, u[c]));
-    }
-
-    const cx<A> mo = cx<A>{-a.o.re, -a.o.im};
-    cx<A> am[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const cx<A> m = mtab[pc * C + c];
-        q[c] = cmul(m, q[c]);
-        am[c] = cmul(mo, m);
-    }
-
-    // forward elimination
-    cx<A> t = cx<A>{0, 0};
-#pragma unroll
-    for (int c = 0; c < C; ++c) t = cfma(am[c], t, q[c]);
+    // forward: local pass, Kogge-Stone over the chunks through LDS, rerun
+    cx<A> t = chunk_forward<REAL, false>(u, zero, a.k);
     __syncthreads();  // every thread has read its neighbours from b0/b1
     cx<A> *cur = b0, *nxt = b1;
     cur[me] = t;
     __syncthreads();
-    for (int stg = 0; stg < a.nst_f; ++stg) {
-        const int d = 1 << stg;
-        if (pc >= d) t = cfma(scan[stg * P + pc], cur[me - d * XT], t);
-        nxt[me] = t;
-        __syncthreads();
-        cx<A> *tmp = cur; cur = nxt; nxt = tmp;
-    }
-    t = pc > 0 ? cur[me - XT] : cx<A>{0, 0};
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        t = cfma(am[c], t, q[c]);
-        q[c] = t;
+    for (int stg = 0; stg < kMaxStages; ++stg) {
+        if (stg < a.k.nst) {
+            const int d = 1 << stg;
+            if (pc >= d) t = kfma<REAL>(a.k.stage[stg], cur[me - d * XT], t);
+            nxt[me] = t;
+            __syncthreads();
+            cx<A> *tmp = cur; cur = nxt; nxt = tmp;
+        }
     }
+    t = pc > 0 ? cur[me - XT] : zero;
+    chunk_forward<REAL, true>(u, t, a.k);
+    if (pos0 + C > a.n) chunk_clear_padding(u, pos0, a.n);
 
-    // back substitution
-    t = cx<A>{0, 0};
-#pragma unroll
-    for (int c = C - 1; c >= 0; --c) t = cfma(am[c], t, q[c]);
+    // backward
+    t = chunk_backward<REAL, false>(u, zero, a.k);
     __syncthreads();  // every thread has read its forward carry
     nxt[me] = t;
     __syncthreads();
     { cx<A> *tmp = cur; cur = nxt; nxt = tmp; }
-    for (int stg = 0; stg < a.nst_b; ++stg) {
-        const int d = 1 << stg;
-        if (pc + d < P) t = cfma(scan[(kMaxStages + stg) * P + pc], cur[me + d * XT], t);
-        nxt[me] = t;
-        __syncthreads();
-        cx<A> *tmp = cur; cur = nxt; nxt = tmp;
-    }
-    t = pc < P - 1 ? cur[me + XT] : cx<A>{0, 0};
 #pragma unroll
-    for (int c = C - 1; c >= 0; --c) {
-        t = cfma(am[c], t, q[c]);
-        q[c] = t;
+    for (int stg = 0; stg < kMaxStages; ++stg) {
+        if (stg < a.k.nst) {
+            const int d = 1 << stg;
+            if (pc + d < P) t = kfma<REAL>(a.k.stage[stg], cur[me + d * XT], t);
+            nxt[me] = t;
+            __syncthreads();
+            cx<A> *tmp = cur; cur = nxt; nxt = tmp;
+        }
     }
+    t = pc < P - 1 ? cur[me + XT] : zero;
+    chunk_backward<REAL, true>(u, t, a.k);
 
+    // boundary correction from the first node of each line
+    __syncthreads();  // every thread has read its backward carry
+    if (pc == 0) nxt[tx] = u[0];
+    __syncthreads();
+    if (pos0 < a.k.nzc) chunk_correct<REAL>(u, nxt[tx], zt, pos0, a.k.nzc);
+
+    if (full) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int pos = pc * C + c;
-        if (act && pos < a.n) base[(int64_t)pos * a.stride] = st<S>(q[c]);
+        for (int c = 0; c < C; ++c) base[(int64_t)c * a.stride] = st<S>(u[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (act && pos0 + c < a.n) base[(int64_t)c * a.stride] = st<S>(u[c]);
     }
 
     if (NORM) {
@@ -121,9 +117,8 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int pos = pc * C + c;
-            if (act && pos < a.n) {
-                const S v = st<S>(q[c]);
+            if (act && pos0 + c < a.n) {
+                const S v = st<S>(u[c]);
                 acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
             }
         }
@@ -145,10 +140,9 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
     }
 }
 
-template <typename S, typename A>
+template <typename S, typename A, bool REAL>
 static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void *args,
-                           const void *m, const void *scan, double *partials,
-                           hipStream_t stream)
+                           const void *zt, double *partials, hipStream_t stream)
 {
     const SArgs<A> &a = *static_cast<const SArgs<A> *>(args);
     const int P = a.lanes;
@@ -157,16 +151,15 @@ static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void 
     const dim3 block((unsigned)xt, (unsigned)P);
     const size_t lds = 2 * (size_t)xt * P * sizeof(cx<A>);
     S *p = static_cast<S *>(psi);
-    const cx<A> *mt = static_cast<const cx<A> *>(m);
-    const cx<A> *sc = static_cast<const cx<A> *>(scan);
-#define GP_S_CASE(CC)                                                                     \
-    case CC:                                                                              \
-        if (partials)                                                                     \
-            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, true>), grid, block, lds, \
-                               stream, p, a, mt, sc, partials);                           \
-        else                                                                              \
-            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, false>), grid, block, lds, \
-                               stream, p, a, mt, sc, partials);                           \
+    const cx<A> *z = static_cast<const cx<A> *>(zt);
+#define GP_S_CASE(CC)                                                                           \
+    case CC:                                                                                    \
+        if (partials)                                                                           \
+            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, true>), grid, block, lds,  \
+                               stream, p, a, z, partials);                                      \
+        else                                                                                    \
+            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, false>), grid, block, lds, \
+                               stream, p, a, z, partials);                                      \
         break;
     switch (chunk) {
         GP_S_CASE(1) GP_S_CASE(2) GP_S_CASE(4) GP_S_CASE(8) GP_S_CASE(16)
@@ -177,18 +170,19 @@ static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void 
     return hipGetLastError();
 }
 
-hipError_t launch_strided(Prec prec, int chunk, int xt, int nouter, void *psi,
-                          const void *args, const void *m, const void *scan,
-                          double *partials, hipStream_t stream)
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, void *psi,
+                          const void *args, const void *zt, double *partials,
+                          hipStream_t stream)
 {
+#define GP_S_PREC(S, A)                                                                  \
+    return real ? launch_t<S, A, true>(chunk, xt, nouter, psi, args, zt, partials, stream) \
+                : launch_t<S, A, false>(chunk, xt, nouter, psi, args, zt, partials, stream);
     switch (prec) {
-    case PREC_C64:
-        return launch_t<float2, float>(chunk, xt, nouter, psi, args, m, scan, partials, stream);
-    case PREC_C64_F64:
-        return launch_t<float2, double>(chunk, xt, nouter, psi, args, m, scan, partials, stream);
-    case PREC_C128:
-        return launch_t<double2, double>(chunk, xt, nouter, psi, args, m, scan, partials, stream);
+    case PREC_C64: GP_S_PREC(float2, float)
+    case PREC_C64_F64: GP_S_PREC(float2, double)
+    case PREC_C128: GP_S_PREC(double2, double)
     }
+#undef GP_S_PREC
     return hipErrorInvalidValue;
 }
 

@@ -98,6 +98,18 @@ def test_steps_match_oracle(grid, mode, dtype):
     assert abs(gobs["norm"] - robs["norm"]) <= tobs * robs["norm"]
 
 
+# Per-observable bounds on the small imaginary-time workload.  mu and E are
+# stationary at the ground state, so the FP32 rounding of psi enters them at
+# second order; the norm is restored every step; the rms sizes are linear in
+# the psi error, whose FP32 level is a few 2^-24, hence 1e-6.
+OBS_TOL_SMALL_IMAG = {
+    "c128": {k: 1e-12 for k in ("mu", "energy", "norm", "rms_x", "rms_y", "rms_z", "rms_r")},
+    "c64": {"mu": 1e-7, "energy": 1e-7, "norm": 1e-7,
+            "rms_x": 1e-6, "rms_y": 1e-6, "rms_z": 1e-6, "rms_r": 1e-6},
+}
+OBS_TOL_SMALL_IMAG["c64_f64"] = OBS_TOL_SMALL_IMAG["c64"]
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_small_imaginary_time_workload(dtype):
     """32^3, dx 0.25, dt 0.1 dx^2, trap (1, 1.4, 2), g 10, Gaussian, 200 steps."""
@@ -105,10 +117,13 @@ def test_small_imaginary_time_workload(dtype):
     psi0 = input_for(dtype, inputs.initial_state(w))
     ref, robs = oracle_run(psi0, w.dx, w.dt, w.omega, w.g, w.mode, w.steps)
     got, gobs = gpu_run(psi0, w.grid, w.dx, w.dt, w.omega, w.g, w.mode, dtype, w.steps, chunks=4)
-    tpsi, tmu = TOL[dtype]
-    assert rel(got, ref) <= tpsi
-    for k in ("mu", "energy", "rms_x", "rms_y", "rms_z", "rms_r", "norm"):
-        assert abs(gobs[k] - robs[k]) <= tmu * abs(robs[k]), k
+    tpsi, _ = TOL[dtype]
+    err = rel(got, ref)
+    print(f"{dtype}: max|dpsi|/max|psi| = {err:.3e}; " +
+          ", ".join(f"{k} {abs(gobs[k] - robs[k]) / abs(robs[k]):.2e}" for k in OBS_TOL_SMALL_IMAG[dtype]))
+    assert err <= tpsi
+    for k, tol in OBS_TOL_SMALL_IMAG[dtype].items():
+        assert abs(gobs[k] - robs[k]) <= tol * abs(robs[k]), k
     assert gobs["steps_done"] == w.steps
 
 

@@ -1,7 +1,7 @@
 """Host-side checks of libgpssc that need no GPU: the exported C ABI, argument
 validation before any device call, the launch-shape policy, and the chunked
-Thomas scheme the sweep kernels run, replayed in numpy with the library's
-own coefficient tables and compared with a dense solve."""
+constant-coefficient scheme the sweep kernels run, replayed in numpy with
+the library's own coefficients and compared with a dense solve."""
 import ctypes
 import os
 import re
@@ -104,84 +104,105 @@ def test_sweep_shapes(n):
 
 
 def dense_cn_rhs_solve(n, tab, psi):
-    A = tab["b"] * np.eye(n) + tab["o"] * (np.eye(n, k=1) + np.eye(n, k=-1))
-    B = tab["rdiag"] * np.eye(n) + tab["roff"] * (np.eye(n, k=1) + np.eye(n, k=-1))
+    kap = tab["kappa"]
+    A = (1 + kap) * np.eye(n) - kap / 2 * (np.eye(n, k=1) + np.eye(n, k=-1))
+    B = (1 - kap) * np.eye(n) + kap / 2 * (np.eye(n, k=1) + np.eye(n, k=-1))
     return np.linalg.solve(A, B @ psi)
 
 
 def chunked_solve(tab, n, chunk, lanes, psi, stages=None):
-    """The sweep kernels' scheme: per-chunk Thomas with zero carry, Kogge-Stone
-    over chunks with the library's stage multipliers, rerun from the carry."""
+    """The sweep kernels' scheme, replayed with the library's coefficients:
+    per-chunk recurrences with a zero carry, Kogge-Stone over the chunks,
+    rerun from the carry, padding cleared, then the boundary correction."""
     npad = chunk * lanes
     u = np.zeros(npad, complex)
     u[:n] = psi
     left = np.concatenate([[0], u[:-1]])
     right = np.concatenate([u[1:], [0]])
-    q = tab["rdiag"] * u + tab["roff"] * (left + right)
-    m = tab["m"]
-    a = -tab["o"] * m
-    mq = m * q
-    scan = tab["scan"]
+    kap = tab["kappa"]
+    r = u + kap * ((left + right) / 2 - u)
+    mr = tab["m"] * r
+    a = tab["a"]
+    st = tab["stage"]
     if stages is None:
-        stages = [int(np.max(np.nonzero(np.any(scan[dr] != 0, axis=1))[0], initial=-1)) + 1 for dr in (0, 1)]
+        stages = 0
+        for s in range(6):
+            if (1 << s) < lanes and st[s] != 0 and stages == s:
+                stages = s + 1
 
-    def local(carry, k, values, backward):
+    def run(vals, carry, k, backward):
         idx = range(k * chunk, (k + 1) * chunk)
-        idx = reversed(list(idx)) if backward else idx
+        idx = list(reversed(idx)) if backward else list(idx)
         t = carry
-        out = np.zeros(npad, complex)
+        out = {}
         for i in idx:
-            t = values[i] + a[i] * t
+            t = vals[i] + a * t
             out[i] = t
         return t, out
 
-    L = np.array([local(0, k, mq, False)[0] for k in range(lanes)])
-    F = L.copy()
-    for s in range(stages[0]):
+    L = [run(mr, 0, k, False)[0] for k in range(lanes)]
+    F = list(L)
+    for s in range(stages):
         d = 1 << s
-        F = np.array([F[k] + (scan[0, s, k] * F[k - d] if k >= d else 0) for k in range(lanes)])
-    dvals = np.zeros(npad, complex)
+        F = [F[k] + (st[s] * F[k - d] if k >= d else 0) for k in range(lanes)]
+    w = np.zeros(npad, complex)
     for k in range(lanes):
-        _, o = local(F[k - 1] if k > 0 else 0, k, mq, False)
-        dvals += o
-    U = np.array([local(0, k, dvals, True)[0] for k in range(lanes)])
-    R = U.copy()
-    for s in range(stages[1]):
+        for i, v in run(mr, F[k - 1] if k > 0 else 0, k, False)[1].items():
+            w[i] = v
+    w[n:] = 0
+    U = [run(w, 0, k, True)[0] for k in range(lanes)]
+    R = list(U)
+    for s in range(stages):
         d = 1 << s
-        R = np.array([R[k] + (scan[1, s, k] * R[k + d] if k + d < lanes else 0) for k in range(lanes)])
-    x = np.zeros(npad, complex)
+        R = [R[k] + (st[s] * R[k + d] if k + d < lanes else 0) for k in range(lanes)]
+    y = np.zeros(npad, complex)
     for k in range(lanes):
-        _, o = local(R[k + 1] if k + 1 < lanes else 0, k, dvals, True)
-        x += o
-    return x[:n]
+        for i, v in run(w, R[k + 1] if k + 1 < lanes else 0, k, True)[1].items():
+            y[i] = v
+    x = y[:n] + y[0] * tab["zt"]
+    return x
 
 
 @pytest.mark.parametrize("mode", ["imag", "real"])
-@pytest.mark.parametrize("n,dx,dt", [(1, 0.25, 0.006), (7, 0.25, 0.006), (32, 0.25, 0.00625),
-                                     (200, 0.1, 5e-5), (240, 0.1, 0.01), (384, 0.05, 1.25e-5),
-                                     (512, 0.05, 0.25), (97, 0.1, 1.0)])
-def test_chunked_thomas_with_library_tables_matches_dense_solve(mode, n, dx, dt):
+@pytest.mark.parametrize("n,dx,dt", [(1, 0.25, 0.006), (2, 0.25, 0.006), (7, 0.25, 0.006),
+                                     (32, 0.25, 0.00625), (200, 0.1, 5e-5), (240, 0.1, 0.01),
+                                     (384, 0.05, 1.25e-5), (512, 0.05, 0.25), (97, 0.1, 1.0),
+                                     (130, 0.05, 0.5)])
+def test_chunked_solve_with_library_coefficients_matches_dense_solve(mode, n, dx, dt):
     rng = np.random.default_rng(n)
     psi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     for axis in (0, 1):
         chunk, lanes = gp.sweep_shape(n, axis)
         tab = gp.sweep_tables(n, dx, dt, mode, chunk, lanes)
-        assert np.all(tab["m"][n:] == 0)
         ref = dense_cn_rhs_solve(n, tab, psi)
         x = chunked_solve(tab, n, chunk, lanes, psi)
-        assert np.max(np.abs(x - ref)) <= 1e-14 * np.max(np.abs(ref))
-        # skipping the all-zero stages changes nothing
-        if lanes > 1:
-            full = chunked_solve(tab, n, chunk, lanes, psi, stages=[6, 6])
+        assert np.max(np.abs(x - ref)) <= 1e-14 * np.max(np.abs(ref)), axis
+        if lanes > 1:   # dropping the stages whose multiplier is zero changes nothing
+            full = chunked_solve(tab, n, chunk, lanes, psi, stages=min(6, (lanes - 1).bit_length()))
             assert np.array_equal(full, x)
 
 
-def test_sweep_table_coefficients():
-    tab = gp.sweep_tables(10, 0.5, 0.1, "real", 1, 10)
-    kappa = 1j * 0.1 / (2 * 0.25)
-    assert tab["b"] == 1 + kappa and tab["o"] == -kappa / 2
-    assert tab["rdiag"] == 1 - kappa and tab["roff"] == kappa / 2
-    assert abs(tab["m"][0] - 1 / (1 + kappa)) < 1e-16
+@pytest.mark.parametrize("mode", ["imag", "real"])
+@pytest.mark.parametrize("kap", [1e-6, 0.0025, 0.05, 1.0, 100.0])
+def test_constant_coefficient_factorisation(mode, kap):
+    n = 9
+    dx = 1.0
+    dt = 2 * kap
+    tab = gp.sweep_tables(n, dx, dt, mode, 1, n)
+    kappa = (1j if mode == "real" else 1) * kap
+    assert abs(tab["kappa"] - kappa) <= 1e-15 * kap
+    assert abs(tab["c"]) < 1
+    S = np.eye(n, k=-1)
+    I = np.eye(n)
+    A = (1 + kappa) * I - kappa / 2 * (S + S.T)
+    fac = tab["beta"] * (I + tab["c"] * S) @ (I + tab["c"] * S.T)
+    fac[0, 0] += tab["beta"] * tab["c"] ** 2
+    assert np.max(np.abs(fac - A)) <= 1e-14 * np.max(np.abs(A))
+    assert abs(tab["m"] * tab["beta"] - 1) <= 1e-15 and tab["a"] == -tab["c"]
+    assert abs(tab["stage"][0] - tab["a"]) <= 1e-16 and abs(tab["stage"][1] - tab["a"] ** 2) <= 1e-15
+
+
+def test_sweep_tables_reject_short_chunking():
     with pytest.raises(gp.GPError):
         gp.sweep_tables(10, 0.5, 0.1, "real", 1, 5)     # chunk * lanes < n
 
