@@ -82,6 +82,47 @@ struct SweepCoef {
     int nzc;                   // zt is nonzero only at positions < nzc
 };
 
+// Streaming loads and stores of psi.  Every sweep reads each element once
+// and writes it once, so the accesses are marked nontemporal: the data are
+// not kept in the caches for reuse that never comes.
+#ifndef GPSSC_NT_LOAD
+#define GPSSC_NT_LOAD 1
+#endif
+#ifndef GPSSC_NT_STORE
+#define GPSSC_NT_STORE 1
+#endif
+template <typename S> struct vec2_of;
+template <> struct vec2_of<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct vec2_of<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+
+template <typename S>
+__device__ __forceinline__ S stream_load(const S *p)
+{
+    typedef typename vec2_of<S>::type V;
+    V v;
+    if (GPSSC_NT_LOAD)
+        v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    else
+        v = *reinterpret_cast<const V *>(p);
+    S r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+
+template <typename S>
+__device__ __forceinline__ void stream_store(S *p, S val)
+{
+    typedef typename vec2_of<S>::type V;
+    V v;
+    v.x = val.x;
+    v.y = val.y;
+    if (GPSSC_NT_STORE)
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    else
+        *reinterpret_cast<V *>(p) = v;
+}
+
 // Launch arguments of the calcnu + calclux kernel.
 template <typename A>
 struct XArgs {
@@ -128,17 +169,17 @@ enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2 };
 
 // calcnu + calclux.  zt: boundary correction by position (complex, the
 // arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
-// nblocks: resident one-wavefront blocks to launch (each loops over lines).
+// nblocks: one-wavefront blocks to launch (each loops over lines; 0 or >= the
+// line count = one per line).
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
                        const void *zt, const double *scale, hipStream_t stream);
 
-// Blocks of the x kernel that fit on the device at once (all compute units).
-int nu_x_resident_blocks(Prec prec, bool real, int chunk);
-
-// calcluy / calcluz.  zt: boundary correction by position.  partials: NULL,
-// or one double per block (sum |psi|^2 of the block's output).
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, void *psi,
-                          const void *args, const void *zt, double *partials,
+// calcluy / calcluz over ceil(nx/xt) x nouter tiles.  nblocks: blocks to
+// launch (each loops over tiles; 0 or >= the tile count = one per tile).
+// zt: boundary correction by position.  partials: NULL, or one double per
+// tile (sum |psi|^2 of the tile's output).
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, int nblocks,
+                          void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream);
 
 // calcnorm: sums `n` partials in a fixed order, writes 1/sqrt(dv*sum) to

@@ -79,6 +79,7 @@ bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes, int max_lanes = gp
 #ifndef GPSSC_YZ_COLS
 #define GPSSC_YZ_COLS 64
 #endif
+
 int strided_columns(int64_t nx, int lanes)
 {
     int xt = GPSSC_YZ_COLS;
@@ -234,7 +235,7 @@ struct gp_plan {
 
     AxisTables ax[3];
     int xt_y, xt_z;
-    int x_blocks;   // resident blocks of the persistent x kernel
+    int x_blocks, y_blocks, z_blocks;   // blocks launched per sweep
 
     unsigned char *d_tables = nullptr;
     size_t tab_off[3];
@@ -533,12 +534,14 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     }
     fill_args<double>(p, p->xd, p->sd);
     fill_args<float>(p, p->xf, p->sf);
-    p->x_blocks = gpssc::nu_x_resident_blocks(static_cast<gpssc::Prec>(dtype), real, chunk[0]);
-    if (p->x_blocks <= 0) {
-        (void)hipGetLastError();
-        release(p);
-        return fail(GP_ERR_DEVICE, "querying the occupancy of the x kernel failed");
-    }
+    // One block per line (x) or tile (y, z): blocks that finish early make
+    // room for the next ones, so the blocks on a compute unit drift out of
+    // step and their load, compute and store phases overlap.  (A grid of
+    // resident blocks looping over the work keeps them in lockstep and was
+    // measured slower.)
+    p->x_blocks = (int)(grid[1] * grid[2]);
+    p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
+    p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
     *out = p;
     return GP_OK;
 }
@@ -597,14 +600,15 @@ gp_status gp_step(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps)
         });
         if (e != hipSuccess) break;
         e = timed(p, GP_KERNEL_Y, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2], psi,
-                                         yargs, T + p->tab_off[1], nullptr, p->stream);
+            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
+                                         p->y_blocks, psi, yargs, T + p->tab_off[1], nullptr,
+                                         p->stream);
         });
         if (e != hipSuccess) break;
         e = timed(p, GP_KERNEL_Z, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1], psi,
-                                         zargs, T + p->tab_off[2], real ? nullptr : p->d_partials,
-                                         p->stream);
+            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
+                                         p->z_blocks, psi, zargs, T + p->tab_off[2],
+                                         real ? nullptr : p->d_partials, p->stream);
         });
         if (e != hipSuccess || real) continue;
         e = timed(p, GP_KERNEL_NORM, [&] {
@@ -708,13 +712,13 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     }
     const char *dt = p->dtype == GP_C64 ? "c64" : (p->dtype == GP_C64_F64 ? "c64/f64" : "c128");
     std::snprintf(buf, len,
-                  "grid %lldx%lldx%lld %s %s | x: chunk %d x 64 lanes, %d stages, correction %d | "
-                  "y: chunk %d x %d lanes, %d cols, %d stages, correction %d | "
-                  "z: chunk %d x %d lanes, %d cols, %d stages, correction %d",
+                  "grid %lldx%lldx%lld %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
+                  "%d blocks | y: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks | "
+                  "z: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks",
                   (long long)p->n[0], (long long)p->n[1], (long long)p->n[2],
                   p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
-                  p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->ax[2].chunk,
-                  p->ax[2].lanes, p->xt_z, nst[2], nzc[2]);
+                  p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->y_blocks,
+                  p->ax[2].chunk, p->ax[2].lanes, p->xt_z, nst[2], nzc[2], p->z_blocks);
     return GP_OK;
 }
 

@@ -126,11 +126,12 @@ __device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row,
         const int e = r * kWave + lane;
         v[r].x = 0;
         v[r].y = 0;
-        if (e < nx) v[r] = row[e];
+        if (e < nx) v[r] = stream_load(row + e);
     }
 }
 
-// One block (one wavefront) per x line.
+// One wavefront per block; block b solves lines b, b + G, ... (G =
+// gridDim.x).  The plan launches one block per line.
 template <typename S, typename A, int C, bool REAL>
 __global__ void __launch_bounds__(kWave)
 calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict__ zt,
@@ -138,16 +139,19 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
 {
     __shared__ S buf[kWave * C + kWave];
     const int lane = threadIdx.x;
-    const int line = blockIdx.x;
+    const int nlines = a.ny * a.nz;
     const A s = scale ? (A)(*scale) : (A)1;
-    S *row = psi + (int64_t)line * a.nx;
-    S v[C];
-    load_x_row(v, row, a.nx);
-    solve_x_line<S, A, C, REAL>(v, buf, a, zt, s, line);
+    for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
+        S *row = psi + (int64_t)line * a.nx;
+        S v[C];
+        load_x_row(v, row, a.nx);
+        solve_x_line<S, A, C, REAL>(v, buf, a, zt, s, line);
 #pragma unroll
-    for (int r = 0; r < C; ++r) {
-        const int e = r * kWave + lane;
-        if (e < a.nx) row[e] = v[r];
+        for (int r = 0; r < C; ++r) {
+            const int e = r * kWave + lane;
+            if (e < a.nx) stream_store(row + e, v[r]);
+        }
+        __syncthreads();  // buf is free for the next line
     }
 }
 
@@ -156,8 +160,8 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
                            const double *scale, hipStream_t stream)
 {
     const XArgs<A> &a = *static_cast<const XArgs<A> *>(args);
-    (void)nblocks;
-    const dim3 grid((unsigned)(a.ny * a.nz));
+    const int nlines = a.ny * a.nz;
+    const dim3 grid((unsigned)(nblocks > 0 && nblocks < nlines ? nblocks : nlines));
     const dim3 block(kWave);
     S *p = static_cast<S *>(psi);
     const cx<A> *z = static_cast<const cx<A> *>(zt);
@@ -175,42 +179,6 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
     }
 #undef GP_X_CASE
     return hipGetLastError();
-}
-
-template <typename S, typename A, bool REAL>
-static int resident_c(int chunk)
-{
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-#define GP_X_OCC(CC)                                                                            \
-    case CC:                                                                                    \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
-                &per, reinterpret_cast<const void *>(calcnu_lux_kernel<S, A, CC, REAL>), kWave, \
-                0) != hipSuccess)                                                               \
-            return 0;                                                                           \
-        break;
-    switch (chunk) {
-        GP_X_OCC(1) GP_X_OCC(2) GP_X_OCC(3) GP_X_OCC(4)
-        GP_X_OCC(5) GP_X_OCC(6) GP_X_OCC(7) GP_X_OCC(8)
-        GP_X_OCC(10) GP_X_OCC(12) GP_X_OCC(14) GP_X_OCC(16)
-    default:
-        return 0;
-    }
-#undef GP_X_OCC
-    return per * cus;
-}
-
-int nu_x_resident_blocks(Prec prec, bool real, int chunk)
-{
-    switch (prec) {
-    case PREC_C64: return real ? resident_c<float2, float, true>(chunk) : resident_c<float2, float, false>(chunk);
-    case PREC_C64_F64:
-        return real ? resident_c<float2, double, true>(chunk) : resident_c<float2, double, false>(chunk);
-    case PREC_C128:
-        return real ? resident_c<double2, double, true>(chunk) : resident_c<double2, double, false>(chunk);
-    }
-    return 0;
 }
 
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,

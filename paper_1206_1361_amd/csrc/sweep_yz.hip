@@ -17,12 +17,13 @@
 
 namespace gpssc {
 
+// One tile: XT neighbouring lines (columns) starting at column `col0`, at
+// outer index `outer` (z for the y sweep, y for the z sweep).
 template <typename S, typename A, int C, bool REAL, bool NORM>
-__global__ void __launch_bounds__(kMaxBlockYZ)
-calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ zt,
-                      double *__restrict__ partials)
+__device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &a,
+                                           const cx<A> *__restrict__ zt, double *__restrict__ partials,
+                                           unsigned char *smem_raw, int tile, int col0, int outer)
 {
-    extern __shared__ unsigned char smem_raw[];
     const int XT = blockDim.x;
     const int P = blockDim.y;
     const int tx = threadIdx.x;
@@ -31,21 +32,21 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
     cx<A> *b1 = b0 + P * XT;
     const int me = pc * XT + tx;
 
-    const int i = blockIdx.x * XT + tx;
+    const int i = col0 + tx;
     const bool act = i < a.nx;
     const int pos0 = pc * C;
     const bool full = act && pos0 + C <= a.n;   // whole chunk inside the line
-    S *base = psi + (int64_t)blockIdx.y * a.outer_stride + i + (int64_t)pos0 * a.stride;
+    S *base = psi + (int64_t)outer * a.outer_stride + i + (int64_t)pos0 * a.stride;
 
     cx<A> u[C];
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = ld<A>(base[(int64_t)c * a.stride]);
+        for (int c = 0; c < C; ++c) u[c] = ld<A>(stream_load(base + (int64_t)c * a.stride));
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             u[c] = cx<A>{0, 0};
-            if (act && pos0 + c < a.n) u[c] = ld<A>(base[(int64_t)c * a.stride]);
+            if (act && pos0 + c < a.n) u[c] = ld<A>(stream_load(base + (int64_t)c * a.stride));
         }
     }
 
@@ -105,11 +106,11 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
 
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) base[(int64_t)c * a.stride] = st<S>(u[c]);
+        for (int c = 0; c < C; ++c) stream_store(base + (int64_t)c * a.stride, st<S>(u[c]));
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (act && pos0 + c < a.n) base[(int64_t)c * a.stride] = st<S>(u[c]);
+            if (act && pos0 + c < a.n) stream_store(base + (int64_t)c * a.stride, st<S>(u[c]));
     }
 
     if (NORM) {
@@ -136,18 +137,37 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
             if (me < h) red[me] += red[me + h];
             __syncthreads();
         }
-        if (me == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        if (me == 0) partials[tile] = red[0];
+    }
+}
+
+// Tiles are numbered column-tile fastest; block b solves tiles b, b + G, ...
+// (G = gridDim.x); the plan launches one block per tile.  LDS is reused from
+// one tile to the next.
+template <typename S, typename A, int C, bool REAL, bool NORM>
+__global__ void __launch_bounds__(kMaxBlockYZ)
+calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ zt,
+                      double *__restrict__ partials, int ncol_tiles, int ntiles)
+{
+    extern __shared__ unsigned char smem_raw[];
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int outer = tile / ncol_tiles;
+        const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x;
+        solve_tile<S, A, C, REAL, NORM>(psi, a, zt, partials, smem_raw, tile, col0, outer);
+        __syncthreads();  // LDS is free for the next tile
     }
 }
 
 template <typename S, typename A, bool REAL>
-static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void *args,
+static hipError_t launch_t(int chunk, int xt, int nouter, int nblocks, void *psi, const void *args,
                            const void *zt, double *partials, hipStream_t stream)
 {
     const SArgs<A> &a = *static_cast<const SArgs<A> *>(args);
     const int P = a.lanes;
     if (xt * P > kMaxBlockYZ || P > kMaxLanesYZ) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.nx + xt - 1) / xt), (unsigned)nouter);
+    const int ncol = (a.nx + xt - 1) / xt;
+    const int ntiles = ncol * nouter;
+    const dim3 grid((unsigned)(nblocks > 0 && nblocks < ntiles ? nblocks : ntiles));
     const dim3 block((unsigned)xt, (unsigned)P);
     const size_t lds = 2 * (size_t)xt * P * sizeof(cx<A>);
     S *p = static_cast<S *>(psi);
@@ -156,10 +176,10 @@ static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void 
     case CC:                                                                                    \
         if (partials)                                                                           \
             hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, true>), grid, block, lds,  \
-                               stream, p, a, z, partials);                                      \
+                               stream, p, a, z, partials, ncol, ntiles);                        \
         else                                                                                    \
             hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, false>), grid, block, lds, \
-                               stream, p, a, z, partials);                                      \
+                               stream, p, a, z, partials, ncol, ntiles);                        \
         break;
     switch (chunk) {
         GP_S_CASE(1) GP_S_CASE(2) GP_S_CASE(4) GP_S_CASE(8) GP_S_CASE(16)
@@ -170,13 +190,13 @@ static hipError_t launch_t(int chunk, int xt, int nouter, void *psi, const void 
     return hipGetLastError();
 }
 
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, void *psi,
-                          const void *args, const void *zt, double *partials,
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, int nblocks,
+                          void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream)
 {
-#define GP_S_PREC(S, A)                                                                  \
-    return real ? launch_t<S, A, true>(chunk, xt, nouter, psi, args, zt, partials, stream) \
-                : launch_t<S, A, false>(chunk, xt, nouter, psi, args, zt, partials, stream);
+#define GP_S_PREC(S, A)                                                                           \
+    return real ? launch_t<S, A, true>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream) \
+                : launch_t<S, A, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
     switch (prec) {
     case PREC_C64: GP_S_PREC(float2, float)
     case PREC_C64_F64: GP_S_PREC(float2, double)
