@@ -120,6 +120,11 @@ gp_status gp_plan_destroy(gp_plan *plan);
  * not depend on g, so nothing is rebuilt. */
 gp_status gp_set_g(gp_plan *plan, double g);
 
+/* Changes the trap frequencies (gamma, nu, lambda >= 0, finite) for the
+ * steps queued after this call and for gp_observables.  The tables do not
+ * depend on the trap, so nothing is rebuilt. */
+gp_status gp_set_trap(gp_plan *plan, double gamma, double nu, double lambda);
+
 /* Changes the stream later work is queued on (hipStream_t or NULL). */
 gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
 
@@ -136,6 +141,17 @@ gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
  * final scaling pass, which equals renormalising after every step up to
  * rounding.  nsteps == 0 queues nothing.  The plan allocates nothing here. */
 gp_status gp_step(gp_plan *plan, void *psi_dev, int64_t psi_elems, int64_t nsteps);
+
+/* gp_step with a time-dependent nonlinearity and trap, for driven dynamics
+ * such as a modulated scattering length g(t) = g0 (1 + eps sin(Omega t)):
+ * step s uses g_steps[s] and the trap (trap_steps[3s], trap_steps[3s+1],
+ * trap_steps[3s+2]) = (gamma, nu, lambda).  Either array may be NULL (the
+ * plan's current value is used); both are host arrays read before this call
+ * returns.  The plan keeps the last step's g and trap.  GP_ERR_INVALID, with
+ * nothing queued, if a scheduled value is non-finite or a frequency is
+ * negative. */
+gp_status gp_step_schedule(gp_plan *plan, void *psi_dev, int64_t psi_elems, int64_t nsteps,
+                           const double *g_steps, const double *trap_steps);
 
 /* Waits for the plan's stream and reports a failure met by queued work:
  * GP_ERR_NONFINITE after a non-finite or zero norm in imaginary time,

@@ -30,7 +30,8 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 
 # Every symbol include/gpssc.h declares.
 EXPORTS = (
-    "gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_stream", "gp_step", "gp_sync",
+    "gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
+    "gp_step_schedule", "gp_sync",
     "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
 )
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(vp)]
     L.gp_plan_destroy.argtypes = [vp]
     L.gp_set_g.argtypes = [vp, dbl]
+    L.gp_set_trap.argtypes = [vp, dbl, dbl, dbl]
+    L.gp_step_schedule.argtypes = [vp, vp, i64, i64, dp, dp]
     L.gp_set_stream.argtypes = [vp, vp]
     L.gp_step.argtypes = [vp, vp, i64, i64]
     L.gp_sync.argtypes = [vp]
@@ -115,7 +118,8 @@ def lib() -> ctypes.CDLL:
     L.gp_sweep_shape.argtypes = [i64, ctypes.c_int, ctypes.c_int, ip, ip]
     L.gp_sweep_tables.argtypes = [i64, dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   dp, sz, dp, sz, dp, sz]
-    for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_stream", "gp_step",
+    for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_step_schedule",
+                 "gp_set_stream", "gp_step",
                  "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
                  "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables"):
         getattr(L, name).restype = ctypes.c_int
@@ -257,6 +261,34 @@ class Plan:
     def set_g(self, g: float) -> None:
         _check(lib().gp_set_g(self._handle, float(g)), "gp_set_g")
         self.g = float(g)
+
+    def set_trap(self, gamma: float, nu: float, lam: float) -> None:
+        _check(lib().gp_set_trap(self._handle, float(gamma), float(nu), float(lam)), "gp_set_trap")
+        self.omega = (float(gamma), float(nu), float(lam))
+
+    def step_schedule(self, psi, g_steps=None, trap_steps=None):
+        """Queue one step per entry of g_steps (and/or rows of trap_steps,
+        shape (n, 3)), each with its own g and trap."""
+        import numpy as np
+
+        ptr, n = self._psi(psi)
+        g_arr = None if g_steps is None else np.ascontiguousarray(g_steps, dtype=np.float64).reshape(-1)
+        t_arr = None if trap_steps is None else np.ascontiguousarray(trap_steps, dtype=np.float64).reshape(-1, 3)
+        if g_arr is None and t_arr is None:
+            raise ValueError("give g_steps, trap_steps or both")
+        nsteps = len(g_arr) if g_arr is not None else len(t_arr)
+        if t_arr is not None and len(t_arr) != nsteps:
+            raise ValueError("g_steps and trap_steps must have the same length")
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp_ = None if g_arr is None else g_arr.ctypes.data_as(dp)
+        tp_ = None if t_arr is None else t_arr.ctypes.data_as(dp)
+        self._use_current_stream()
+        _check(lib().gp_step_schedule(self._handle, ptr, n, nsteps, gp_, tp_), "gp_step_schedule")
+        if g_arr is not None and nsteps:
+            self.g = float(g_arr[-1])
+        if t_arr is not None and nsteps:
+            self.omega = tuple(float(v) for v in t_arr[-1])
+        return psi
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(512)

@@ -390,6 +390,79 @@ gp_status read_flag(gp_plan *p)
     return GP_OK;
 }
 
+void set_g(gp_plan *p, double g)
+{
+    p->g = g;
+    p->xd.g = g;
+    p->xf.g = (float)g;
+}
+
+void set_trap(gp_plan *p, const double om[3])
+{
+    for (int a = 0; a < 3; ++a) p->omega[a] = om[a];
+    p->xd.hgx = 0.5 * om[0] * om[0];
+    p->xd.hgy = 0.5 * om[1] * om[1];
+    p->xd.hgz = 0.5 * om[2] * om[2];
+    p->xf.hgx = (float)p->xd.hgx;
+    p->xf.hgy = (float)p->xd.hgy;
+    p->xf.hgz = (float)p->xd.hgz;
+}
+
+// Queues nsteps steps.  With schedules, step s uses g_steps[s] and the trap
+// trap_steps[3s .. 3s+2]; the plan keeps the last step's values.
+gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, const double *g_steps,
+                    const double *trap_steps)
+{
+    DeviceGuard guard(p->device);
+    gp_status st = check_psi(p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    if (nsteps == 0) return GP_OK;
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(p->dtype);
+    const bool c64 = p->dtype != GP_C128;   // complex64 storage
+    const bool a32 = p->dtype == GP_C64;    // FP32 arithmetic
+    const bool real = p->mode == GP_MODE_REAL;
+    const void *xargs = a32 ? (const void *)&p->xf : (const void *)&p->xd;
+    const void *yargs = a32 ? (const void *)&p->sf[0] : (const void *)&p->sd[0];
+    const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
+    const unsigned char *T = p->d_tables;
+    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        if (g_steps) set_g(p, g_steps[s]);
+        if (trap_steps) set_trap(p, trap_steps + 3 * s);
+        const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
+        e = timed(p, GP_KERNEL_NU_X, [&] {
+            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
+                                      T + p->tab_off[0], scale, p->stream);
+        });
+        if (e != hipSuccess) break;
+        e = timed(p, GP_KERNEL_Y, [&] {
+            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
+                                         p->y_blocks, psi, yargs, T + p->tab_off[1], nullptr,
+                                         p->stream);
+        });
+        if (e != hipSuccess) break;
+        e = timed(p, GP_KERNEL_Z, [&] {
+            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
+                                         p->z_blocks, psi, zargs, T + p->tab_off[2],
+                                         real ? nullptr : p->d_partials, p->stream);
+        });
+        if (e != hipSuccess || real) continue;
+        e = timed(p, GP_KERNEL_NORM, [&] {
+            return gpssc::launch_norm_finalize(p->d_partials, p->n_zblocks, dv, p->d_scale,
+                                               p->d_flag, p->stream);
+        });
+    }
+    if (e == hipSuccess && !real) {
+        const int64_t elems = p->n[0] * p->n[1] * p->n[2];
+        e = timed(p, GP_KERNEL_SCALE,
+                  [&] { return gpssc::launch_scale(c64, psi, elems, p->d_scale, p->stream); });
+    }
+    if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
+    p->steps_done += nsteps;
+    return GP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,9 +634,7 @@ gp_status gp_set_g(gp_plan *plan, double g)
 {
     if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
     if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
-    plan->g = g;
-    plan->xd.g = g;
-    plan->xf.g = (float)g;
+    set_g(plan, g);
     return GP_OK;
 }
 
@@ -574,56 +645,36 @@ gp_status gp_set_stream(gp_plan *plan, void *hip_stream)
     return GP_OK;
 }
 
+gp_status gp_set_trap(gp_plan *plan, double gamma, double nu, double lambda)
+{
+    if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
+    const double om[3] = {gamma, nu, lambda};
+    for (double w : om)
+        if (!std::isfinite(w) || w < 0.0) return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+    set_trap(plan, om);
+    return GP_OK;
+}
+
 gp_status gp_step(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps)
 {
     if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
     if (nsteps < 0) return fail(GP_ERR_INVALID, "nsteps must be >= 0");
-    DeviceGuard guard(p->device);
-    gp_status st = check_psi(p, psi, psi_elems);
-    if (st != GP_OK) return st;
-    if (nsteps == 0) return GP_OK;
-    const gpssc::Prec prec = static_cast<gpssc::Prec>(p->dtype);
-    const bool c64 = p->dtype != GP_C128;   // complex64 storage
-    const bool a32 = p->dtype == GP_C64;    // FP32 arithmetic
-    const bool real = p->mode == GP_MODE_REAL;
-    const void *xargs = a32 ? (const void *)&p->xf : (const void *)&p->xd;
-    const void *yargs = a32 ? (const void *)&p->sf[0] : (const void *)&p->sd[0];
-    const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
-    const unsigned char *T = p->d_tables;
-    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
-    hipError_t e = hipSuccess;
-    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
-        const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
-        e = timed(p, GP_KERNEL_NU_X, [&] {
-            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
-                                      T + p->tab_off[0], scale, p->stream);
-        });
-        if (e != hipSuccess) break;
-        e = timed(p, GP_KERNEL_Y, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
-                                         p->y_blocks, psi, yargs, T + p->tab_off[1], nullptr,
-                                         p->stream);
-        });
-        if (e != hipSuccess) break;
-        e = timed(p, GP_KERNEL_Z, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
-                                         p->z_blocks, psi, zargs, T + p->tab_off[2],
-                                         real ? nullptr : p->d_partials, p->stream);
-        });
-        if (e != hipSuccess || real) continue;
-        e = timed(p, GP_KERNEL_NORM, [&] {
-            return gpssc::launch_norm_finalize(p->d_partials, p->n_zblocks, dv, p->d_scale,
-                                               p->d_flag, p->stream);
-        });
+    return run_steps(p, psi, psi_elems, nsteps, nullptr, nullptr);
+}
+
+gp_status gp_step_schedule(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps,
+                           const double *g_steps, const double *trap_steps)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (nsteps < 0) return fail(GP_ERR_INVALID, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (g_steps && !std::isfinite(g_steps[s])) return fail(GP_ERR_INVALID, "g schedule holds a non-finite value");
+        if (trap_steps)
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(trap_steps[3 * s + a]) || trap_steps[3 * s + a] < 0.0)
+                    return fail(GP_ERR_INVALID, "trap schedule holds a negative or non-finite value");
     }
-    if (e == hipSuccess && !real) {
-        const int64_t elems = p->n[0] * p->n[1] * p->n[2];
-        e = timed(p, GP_KERNEL_SCALE,
-                  [&] { return gpssc::launch_scale(c64, psi, elems, p->d_scale, p->stream); });
-    }
-    if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
-    p->steps_done += nsteps;
-    return GP_OK;
+    return run_steps(p, psi, psi_elems, nsteps, g_steps, trap_steps);
 }
 
 gp_status gp_sync(gp_plan *p)

@@ -260,3 +260,30 @@ def test_quench_grid_full_comparison(dtype):
     tpsi, tmu = TOL[dtype]
     assert rel(got, ref) <= tpsi
     assert abs(gobs["mu"] - robs["mu"]) <= tmu * abs(robs["mu"])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["real", "imag"])
+def test_modulated_g_and_trap_schedule_matches_oracle(mode, dtype):
+    """g(t) = g0 (1 + eps sin(Omega t)) and a breathing trap, one value per
+    step, against the oracle stepped once per scheduled value."""
+    grid, dx = (40, 36, 30), (0.3, 0.3, 0.3)
+    omega0 = np.array([1.0, 1.3, 1.7])
+    dt = 0.004 if mode == "real" else 0.02
+    n = 12
+    t = dt * np.arange(n)
+    g_sched = 15.0 * (1 + 0.4 * np.sin(3.0 * t))
+    trap_sched = omega0[None, :] * (1 + 0.1 * np.cos(2.0 * t))[:, None]
+    psi0 = input_for(dtype, inputs.smooth_random_state(grid, dx, tuple(omega0), seed=31))
+    ref = psi0.copy()
+    for s in range(n):
+        oracle.step(ref, dx, dt, tuple(trap_sched[s]), g_sched[s], MODES[mode], 1)
+    robs = oracle.observables(ref, dx, tuple(trap_sched[-1]), g_sched[-1])
+    psi = to_dev(psi0, dtype)
+    with gp.Plan(grid, dx, dt, *omega0, 1.0, mode=mode, dtype=dtype) as plan:
+        plan.step_schedule(psi, g_sched[:5], trap_sched[:5])
+        plan.step_schedule(psi, g_sched[5:], trap_sched[5:])
+        gobs = plan.observables(psi)
+    tpsi, _ = TOL[dtype]
+    assert rel(to_host(psi), ref) <= tpsi
+    assert abs(gobs["mu"] - robs["mu"]) <= TOL_OBS_SMALL[dtype] * abs(robs["mu"])
