@@ -194,6 +194,65 @@ gp_status gp_profile_read(gp_plan *plan, double *ms, int64_t *launches);
  * (64 for x).  Host only.  GP_ERR_UNSUPPORTED if the line is too long. */
 gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *lanes);
 
+/* ---- Batches: many independent solves advanced together ---------------
+ *
+ * For throughput on grids too small to fill the GPU alone (the ground states
+ * of a parameter scan, the requests of a service): the solves of a batch
+ * share mode and dtype but each has its own grid, spacings, step, trap and
+ * g.  Solves with the same grid shape form a class; every sweep is one
+ * launch per class covering all its active solves.  Each solve's result is
+ * bitwise the one a gp_plan with the same parameters gives.  The batch
+ * queues work on a stream of its own, ordered after the caller's stream at
+ * the start of every call and before it at the end. */
+typedef struct gp_batch gp_batch;
+
+enum {
+    GP_BATCH_GRAPH = 1,  /* capture one step of all classes in a HIP graph and replay it */
+    GP_BATCH_TUNE = 2    /* time the y/z block widths per class at creation (scratch memory) */
+};
+
+/* Creates a batch of nsolves solves.  Per solve i: grids[3i..3i+2] (Nx, Ny,
+ * Nz, each 1..1024), dx[3i..3i+2] > 0, dt[i] > 0, traps[3i..3i+2] >= 0,
+ * g[i] finite.  flags: GP_BATCH_* bits.  hip_stream: the caller's stream
+ * (NULL: the null stream).  GP_ERR_INVALID / _UNSUPPORTED / _NOMEM /
+ * _DEVICE on failure with *out = NULL. */
+gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, const double *dt,
+                          const double *traps, const double *g, gp_mode mode, gp_dtype dtype,
+                          int flags, void *hip_stream, gp_batch **out);
+
+/* Waits for the batch's work and frees it.  NULL-safe. */
+gp_status gp_batch_destroy(gp_batch *batch);
+
+/* Binds solve i to the caller-owned device array psi[i] of elems[i]
+ * complex numbers (the layout and alignment of gp_step).  Must precede
+ * gp_batch_step; may be repeated to rebind. */
+gp_status gp_batch_set_psi(gp_batch *batch, void *const *psi, const int64_t *elems);
+
+/* Selects the solves later calls advance and measure: mask[i] != 0 (NULL:
+ * all).  Inactive solves are left untouched. */
+gp_status gp_batch_set_active(gp_batch *batch, const unsigned char *mask);
+
+/* Queues nsteps split-step Crank-Nicolson steps of every active solve (in
+ * imaginary time each ends normalised, as gp_step). */
+gp_status gp_batch_step(gp_batch *batch, int64_t nsteps);
+
+/* Physical quantities of every active solve into out[i] (inactive entries
+ * are not written); waits for them.  GP_ERR_NONFINITE if any solve's norm
+ * or quantity is not finite (all entries still filled). */
+gp_status gp_batch_observables(gp_batch *batch, gp_obs *out);
+
+/* Imaginary-time ground states with a per-solve stopping rule: every
+ * check_every steps the chemical potentials are evaluated, and a solve
+ * whose mu moved by less than tol since the previous evaluation stops (is
+ * no longer advanced).  Ends when all solves stopped or after max_steps.
+ * Fills out[i] (last evaluation), steps[i] (steps taken) and converged[i].
+ * Every solve is active again on return. */
+gp_status gp_batch_solve_imag(gp_batch *batch, double tol, int64_t check_every, int64_t max_steps,
+                              gp_obs *out, int64_t *steps, unsigned char *converged);
+
+/* One-line description of the classes and launch shapes. */
+gp_status gp_batch_describe(const gp_batch *batch, char *buf, size_t len);
+
 /* Host-only view of the constant coefficients the sweep kernels use along
  * one axis (no device call), for inspection and tests.  For a line of n
  * points, spacing dx, step dt, mode and a chunking with chunk * lanes >= n,

@@ -8,6 +8,7 @@ loaded on first use, so importing the package (or its seeded input
 generators in ``inputs``) needs no GPU.
 """
 from ._binding import (  # noqa: F401
-    C64, C64_F64, C128, IMAG, REAL, EXPORTS, KERNELS, GPError, GPInvalid, GPNoMemory, GPNonFinite, Plan,
+    C64, C64_F64, C128, IMAG, REAL, EXPORTS, KERNELS, Batch, GPError, GPInvalid, GPNoMemory, GPNonFinite,
+    Plan,
     footprint_bytes, lib, library_path, sweep_shape, sweep_tables,
 )

@@ -34,7 +34,12 @@ EXPORTS = (
     "gp_step_schedule", "gp_sync",
     "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
+    "gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active", "gp_batch_step",
+    "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe",
 )
+
+BATCH_GRAPH = 1
+BATCH_TUNE = 2
 
 
 class GPError(RuntimeError):
@@ -118,6 +123,19 @@ def lib() -> ctypes.CDLL:
     L.gp_sweep_shape.argtypes = [i64, ctypes.c_int, ctypes.c_int, ip, ip]
     L.gp_sweep_tables.argtypes = [i64, dbl, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   dp, sz, dp, sz, dp, sz]
+    up = ctypes.POINTER(ctypes.c_ubyte)
+    L.gp_batch_create.argtypes = [ctypes.c_int, i64p, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  vp, ctypes.POINTER(vp)]
+    L.gp_batch_destroy.argtypes = [vp]
+    L.gp_batch_set_psi.argtypes = [vp, ctypes.POINTER(vp), i64p]
+    L.gp_batch_set_active.argtypes = [vp, up]
+    L.gp_batch_step.argtypes = [vp, i64]
+    L.gp_batch_observables.argtypes = [vp, ctypes.POINTER(GPObs)]
+    L.gp_batch_solve_imag.argtypes = [vp, dbl, i64, i64, ctypes.POINTER(GPObs), i64p, up]
+    L.gp_batch_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    for name in ("gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active",
+                 "gp_batch_step", "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_step_schedule",
                  "gp_set_stream", "gp_step",
                  "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
@@ -308,6 +326,100 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_handle", None) and self._handle.value:
             lib().gp_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Independent solves advanced together (gp_batch_*).
+
+    specs: sequence of dicts with keys grid (Nx, Ny, Nz), dx (scalar or
+    3-tuple), dt, trap (gamma, nu, lambda), g.  All share mode and dtype.
+    """
+
+    def __init__(self, specs, mode="imag", dtype="c128", graph=True, tune=False, stream=None):
+        import numpy as np
+        import torch
+
+        L = lib()
+        self.specs = [dict(sp) for sp in specs]
+        n = len(self.specs)
+        if n < 1:
+            raise ValueError("a batch needs at least one solve")
+        grids = np.array([[int(v) for v in sp["grid"]] for sp in self.specs], dtype=np.int64)
+        dxs = np.array([[float(v) for v in (sp["dx"] if hasattr(sp["dx"], "__len__") else (sp["dx"],) * 3)]
+                        for sp in self.specs], dtype=np.float64)
+        dts = np.array([float(sp["dt"]) for sp in self.specs], dtype=np.float64)
+        traps = np.array([[float(v) for v in sp["trap"]] for sp in self.specs], dtype=np.float64)
+        gs = np.array([float(sp["g"]) for sp in self.specs], dtype=np.float64)
+        self.grids = [tuple(int(v) for v in row) for row in grids]
+        self.mode = _mode(mode)
+        self.dtype = _dtype(dtype)
+        self.torch_dtype = torch.complex128 if self.dtype == C128 else torch.complex64
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0)
+        self._handle = ctypes.c_void_p()
+        self._psis = None
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(L.gp_batch_create(n, grids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 dxs.ctypes.data_as(dp), dts.ctypes.data_as(dp), traps.ctypes.data_as(dp),
+                                 gs.ctypes.data_as(dp), self.mode, self.dtype, flags,
+                                 Plan._stream_handle(stream), ctypes.byref(self._handle)),
+               "gp_batch_create")
+        self.n = n
+
+    def bind(self, psis):
+        """Bind solve i to the torch tensor psis[i] (kept referenced)."""
+        if len(psis) != self.n:
+            raise ValueError(f"need {self.n} tensors")
+        for t, g in zip(psis, self.grids):
+            if t.dtype != self.torch_dtype or t.device.type != "cuda" or tuple(t.shape) != g[::-1] \
+                    or not t.is_contiguous():
+                raise ValueError(f"each psi must be a contiguous {self.torch_dtype} CUDA tensor of shape (Nz, Ny, Nx)")
+        ptrs = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in psis])
+        elems = (ctypes.c_int64 * self.n)(*[t.numel() for t in psis])
+        _check(lib().gp_batch_set_psi(self._handle, ptrs, elems), "gp_batch_set_psi")
+        self._psis = list(psis)
+
+    def set_active(self, mask=None):
+        arr = None if mask is None else (ctypes.c_ubyte * self.n)(*[1 if m else 0 for m in mask])
+        _check(lib().gp_batch_set_active(self._handle, arr), "gp_batch_set_active")
+
+    def step(self, nsteps: int = 1):
+        _check(lib().gp_batch_step(self._handle, int(nsteps)), "gp_batch_step")
+
+    def observables(self):
+        out = (GPObs * self.n)()
+        _check(lib().gp_batch_observables(self._handle, out), "gp_batch_observables")
+        return [o.as_dict() for o in out]
+
+    def solve_imag(self, tol: float, check_every: int, max_steps: int):
+        """Per-solve |dmu| < tol stopping; returns (observables, steps, converged)."""
+        out = (GPObs * self.n)()
+        steps = (ctypes.c_int64 * self.n)()
+        conv = (ctypes.c_ubyte * self.n)()
+        _check(lib().gp_batch_solve_imag(self._handle, float(tol), int(check_every), int(max_steps), out,
+                                         steps, conv), "gp_batch_solve_imag")
+        return [o.as_dict() for o in out], list(steps), [bool(c) for c in conv]
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().gp_batch_describe(self._handle, buf, len(buf)), "gp_batch_describe")
+        return buf.value.decode()
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) and self._handle.value:
+            lib().gp_batch_destroy(self._handle)
             self._handle = ctypes.c_void_p()
 
     def __del__(self):

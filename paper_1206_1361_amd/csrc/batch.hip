@@ -1,0 +1,761 @@
+// batch.hip -- many independent solves advanced together (gp_batch_*).
+//
+// Solves with the same grid shape form a class; one launch per class and
+// sweep covers every active solve of the class, reading each solve's psi
+// pointer, coefficients and trap from device arrays.  A step of all classes
+// is captured once into a HIP graph and replayed.  Every per-solve number
+// comes from the same device functions as a single plan (gp_plan_*), so a
+// solve gives bitwise the same result alone and inside a batch.
+//
+// Paper: the split-step Crank-Nicolson step of program summaries (v) and
+// (xiv) ("Method of solution"), with calcnu, calclux/y/z, calcnorm and
+// calcmuen/calcrms as named in "Summary of revisions".
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "gp_internal.h"
+#include "gpssc.h"
+#include "host_common.h"
+
+using namespace gpssc_host;
+
+namespace {
+
+struct Solve {
+    int64_t grid[3];
+    double dx[3], dt, omega[3], g;
+    AxisTables ax[3];
+    int cls;
+    int64_t elems;
+    int64_t part_off;        // into the per-line norm partials
+    int64_t zt_off[3];       // bytes into the correction tables
+    void *psi = nullptr;
+};
+
+struct Class {
+    int64_t grid[3];
+    int chunk[3], lanes[3];
+    int xt_y, xt_z;
+    int nlines, ncol_y, ntiles_y, ncol_z, ntiles_z, obs_blocks;
+    std::vector<int> members;
+    int nact = 0;
+    int *d_active = nullptr;     // active solve indices
+};
+
+}  // namespace
+
+struct gp_batch {
+    int n = 0;
+    gp_mode mode;
+    gp_dtype dtype;
+    int flags = 0;
+    int device = 0;
+    hipStream_t caller = nullptr;   // ordering with the caller's work
+    hipStream_t own = nullptr;      // the batch's queue (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<Solve> s;
+    std::vector<Class> cls;
+    std::vector<unsigned char> active;
+
+    unsigned char *d_tables = nullptr;
+    unsigned char *d_xargs = nullptr, *d_yargs = nullptr, *d_zargs = nullptr;
+    void **d_psis = nullptr;
+    double *d_partials = nullptr;
+    int64_t *d_part_off = nullptr;
+    double *d_dv = nullptr;
+    double *d_scales = nullptr;
+    int *d_flags = nullptr;
+    gpssc::ObsArgs<double> *d_obsargs = nullptr;
+    double *d_obs_partials = nullptr;
+    double *d_sums = nullptr;
+    double *h_sums = nullptr;   // pinned
+    int *h_flags = nullptr;     // pinned
+    void **h_psis = nullptr;    // pinned
+    int *h_active = nullptr;    // pinned, staging for the class lists
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_ok = false;
+    int64_t steps_done = 0;
+};
+
+namespace {
+
+bool bound(const gp_batch *b)
+{
+    for (const Solve &x : b->s)
+        if (!x.psi) return false;
+    return true;
+}
+
+void release(gp_batch *b)
+{
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (Class &c : b->cls)
+        if (c.d_active) hipFree(c.d_active);
+    void *dev[] = {b->d_tables, b->d_xargs, b->d_yargs, b->d_zargs, b->d_psis, b->d_partials,
+                   b->d_part_off, b->d_dv, b->d_scales, b->d_flags, b->d_obsargs,
+                   b->d_obs_partials, b->d_sums};
+    for (void *p : dev)
+        if (p) hipFree(p);
+    void *host[] = {b->h_sums, b->h_flags, b->h_psis, b->h_active};
+    for (void *p : host)
+        if (p) hipHostFree(p);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->own) hipStreamDestroy(b->own);
+    delete b;
+}
+
+template <typename A>
+void fill_solve_args(const Solve &x, const unsigned char *d_tables, gpssc::XBatchArgs<A> &xa,
+                     gpssc::SBatchArgs<A> &ya, gpssc::SBatchArgs<A> &za, const Class &c)
+{
+    gpssc::XArgs<A> &a = xa.x;
+    a.nx = (int)x.grid[0];
+    a.ny = (int)x.grid[1];
+    a.nz = (int)x.grid[2];
+    a.c0x = (A)(0.5 * (double)(x.grid[0] - 1));
+    a.c0y = (A)(0.5 * (double)(x.grid[1] - 1));
+    a.c0z = (A)(0.5 * (double)(x.grid[2] - 1));
+    a.dx = (A)x.dx[0];
+    a.dy = (A)x.dx[1];
+    a.dz = (A)x.dx[2];
+    a.hgx = (A)(0.5 * x.omega[0] * x.omega[0]);
+    a.hgy = (A)(0.5 * x.omega[1] * x.omega[1]);
+    a.hgz = (A)(0.5 * x.omega[2] * x.omega[2]);
+    a.dt = (A)x.dt;
+    a.g = (A)x.g;
+    a.k = sweep_coef<A>(x.ax[0], x.dt, x.dx[0]);
+    xa.zt = reinterpret_cast<const cx<A> *>(d_tables + x.zt_off[0]);
+    gpssc::SBatchArgs<A> *yz[2] = {&ya, &za};
+    for (int ax = 1; ax < 3; ++ax) {
+        gpssc::SArgs<A> &t = yz[ax - 1]->s;
+        t.nx = (int)x.grid[0];
+        t.n = (int)x.grid[ax];
+        t.lanes = c.lanes[ax];
+        t.stride = ax == 1 ? x.grid[0] : x.grid[0] * x.grid[1];
+        t.outer_stride = ax == 1 ? x.grid[0] * x.grid[1] : x.grid[0];
+        t.k = sweep_coef<A>(x.ax[ax], x.dt, x.dx[ax]);
+        yz[ax - 1]->zt = reinterpret_cast<const cx<A> *>(d_tables + x.zt_off[ax]);
+    }
+}
+
+template <typename A>
+std::vector<unsigned char> pack_batch_args(const gp_batch *b, int which)
+{
+    std::vector<unsigned char> out;
+    for (const Solve &x : b->s) {
+        gpssc::XBatchArgs<A> xa;
+        gpssc::SBatchArgs<A> ya, za;
+        fill_solve_args<A>(x, b->d_tables, xa, ya, za, b->cls[(size_t)x.cls]);
+        const unsigned char *p;
+        size_t len;
+        if (which == 0) {
+            p = reinterpret_cast<const unsigned char *>(&xa);
+            len = sizeof xa;
+        } else if (which == 1) {
+            p = reinterpret_cast<const unsigned char *>(&ya);
+            len = sizeof ya;
+        } else {
+            p = reinterpret_cast<const unsigned char *>(&za);
+            len = sizeof za;
+        }
+        out.insert(out.end(), p, p + len);
+    }
+    return out;
+}
+
+// Uploads the active list of every class (pinned staging, stream-ordered on
+// the batch's own queue, then waits so the staging can be reused).
+hipError_t upload_active(gp_batch *b)
+{
+    int off = 0;
+    for (Class &c : b->cls) {
+        c.nact = 0;
+        for (int m : c.members)
+            if (b->active[(size_t)m]) b->h_active[off + c.nact++] = m;
+        off += (int)c.members.size();
+    }
+    off = 0;
+    for (Class &c : b->cls) {
+        if (c.nact) {
+            hipError_t e = hipMemcpyAsync(c.d_active, b->h_active + off, sizeof(int) * (size_t)c.nact,
+                                          hipMemcpyHostToDevice, b->own);
+            if (e != hipSuccess) return e;
+        }
+        off += (int)c.members.size();
+    }
+    return hipStreamSynchronize(b->own);
+}
+
+// One step of every active solve, queued on the batch's own stream.
+hipError_t enqueue_step(gp_batch *b)
+{
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(b->dtype);
+    const bool real = b->mode == GP_MODE_REAL;
+    hipError_t e = hipSuccess;
+    for (const Class &c : b->cls) {
+        if (!c.nact) continue;
+        e = gpssc::launch_nu_x_batch(prec, real, c.chunk[0], c.nact, c.nlines, b->d_psis, b->d_xargs,
+                                     c.d_active, real ? nullptr : b->d_scales, b->own);
+        if (e != hipSuccess) return e;
+        e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.lanes[1], c.nact, c.ncol_y,
+                                        c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr,
+                                        nullptr, b->own);
+        if (e != hipSuccess) return e;
+        e = gpssc::launch_strided_batch(prec, real, c.chunk[2], c.xt_z, c.lanes[2], c.nact, c.ncol_z,
+                                        c.ntiles_z, b->d_psis, b->d_zargs, c.d_active,
+                                        real ? nullptr : b->d_partials, b->d_part_off, b->own);
+        if (e != hipSuccess) return e;
+        if (!real) {
+            e = gpssc::launch_norm_finalize_batch(c.nact, c.d_active, b->d_partials, b->d_part_off,
+                                                  (int)(c.grid[0] * c.grid[1]), b->d_dv, b->d_scales,
+                                                  b->d_flags, b->own);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return e;
+}
+
+hipError_t build_graph(gp_batch *b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_ok = false;
+    hipError_t e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue_step(b);
+    e = hipStreamEndCapture(b->own, &b->graph);
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return e;
+    b->graph_ok = true;
+    return hipSuccess;
+}
+
+// Launch shapes of the y/z sweeps per class: the number of columns per
+// block that runs fastest on this device, timed on scratch memory of one
+// solve's size (the choice does not change any result: each column's
+// arithmetic and its norm partial are independent of it).
+template <typename S>
+hipError_t tune_class(gp_batch *b, Class &c)
+{
+    const Solve &x = b->s[(size_t)c.members[0]];
+    void *scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, sizeof(S) * (size_t)x.elems);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(scratch, 0, sizeof(S) * (size_t)x.elems, b->own);
+    int *d_one = nullptr;
+    void **d_ptr = nullptr;
+    const int zero = 0;
+    if (e == hipSuccess) e = hipMalloc(&d_one, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&d_ptr, sizeof(void *) * (size_t)b->n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_one, &zero, sizeof(int), hipMemcpyHostToDevice, b->own);
+    // a pointer table whose entry for the first member is the scratch
+    std::vector<void *> tab((size_t)b->n, scratch);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ptr, tab.data(), sizeof(void *) * tab.size(), hipMemcpyHostToDevice, b->own);
+    int m0 = c.members[0];
+    int *d_m0 = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d_m0, sizeof(int));
+    if (e == hipSuccess) e = hipMemcpyAsync(d_m0, &m0, sizeof(int), hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(b->dtype);
+    const bool real = b->mode == GP_MODE_REAL;
+    for (int ax = 1; ax < 3 && e == hipSuccess; ++ax) {
+        const int lanes = c.lanes[ax];
+        const int nouter = (int)(ax == 1 ? c.grid[2] : c.grid[1]);
+        int best = ax == 1 ? c.xt_y : c.xt_z;
+        float best_ms = 1e30f;
+        for (int xt : {16, 32, 64}) {
+            if (xt * lanes > gpssc::kMaxBlockYZ) continue;
+            if (xt > 16 && xt / 2 >= c.grid[0]) continue;
+            const int ncol = (int)((c.grid[0] + xt - 1) / xt);
+            const void *args = ax == 1 ? (const void *)b->d_yargs : (const void *)b->d_zargs;
+            double *parts = (ax == 2 && !real) ? b->d_partials : nullptr;
+            auto run = [&] {
+                return gpssc::launch_strided_batch(prec, real, c.chunk[ax], xt, lanes, 1, ncol, ncol * nouter,
+                                                   d_ptr, args, d_m0, parts, b->d_part_off, b->own);
+            };
+            e = run();  // warm
+            if (e != hipSuccess) break;
+            e = hipEventRecord(t0, b->own);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+            if (e == hipSuccess) e = hipEventRecord(t1, b->own);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = xt;
+            }
+        }
+        if (ax == 1)
+            c.xt_y = best;
+        else
+            c.xt_z = best;
+    }
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    if (d_m0) hipFree(d_m0);
+    if (d_ptr) hipFree(d_ptr);
+    if (d_one) hipFree(d_one);
+    hipFree(scratch);
+    return e;
+}
+
+void class_shapes(Class &c)
+{
+    c.nlines = (int)(c.grid[1] * c.grid[2]);
+    c.ncol_y = (int)((c.grid[0] + c.xt_y - 1) / c.xt_y);
+    c.ntiles_y = c.ncol_y * (int)c.grid[2];
+    c.ncol_z = (int)((c.grid[0] + c.xt_z - 1) / c.xt_z);
+    c.ntiles_z = c.ncol_z * (int)c.grid[1];
+    c.obs_blocks = gpssc::obs_num_blocks((int)c.grid[0], (int)c.grid[1]);
+}
+
+hipError_t sync_in(gp_batch *b)
+{
+    hipError_t e = hipEventRecord(b->ev_in, b->caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_in, 0);
+    return e;
+}
+
+hipError_t sync_out(gp_batch *b)
+{
+    hipError_t e = hipEventRecord(b->ev_out, b->own);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->caller, b->ev_out, 0);
+    return e;
+}
+
+gp_status obs_from_sums(const double *S, const Solve &x, gp_obs *out, int64_t steps)
+{
+    const double dv = x.dx[0] * x.dx[1] * x.dx[2];
+    const double norm = dv * S[gpssc::OBS_DENS];
+    const double kin = 0.5 * dv *
+                       (S[gpssc::OBS_LINKX] / (x.dx[0] * x.dx[0]) + S[gpssc::OBS_LINKY] / (x.dx[1] * x.dx[1]) +
+                        S[gpssc::OBS_LINKZ] / (x.dx[2] * x.dx[2]));
+    const double pot = dv * S[gpssc::OBS_POT];
+    const double inter = x.g * dv * S[gpssc::OBS_QUART];
+    out->norm = norm;
+    out->kinetic = kin / norm;
+    out->potential = pot / norm;
+    out->interaction = inter / (norm * norm);
+    out->energy = out->kinetic + out->potential + 0.5 * out->interaction;
+    out->mu = out->kinetic + out->potential + out->interaction;
+    double r2 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        const double m2 = dv * S[gpssc::OBS_M2X + q] / norm;
+        out->rms[q] = std::sqrt(m2);
+        out->mean[q] = dv * S[gpssc::OBS_M1X + q] / norm;
+        r2 += m2;
+    }
+    out->rms_r = std::sqrt(r2);
+    out->steps_done = steps;
+    bool ok = norm > 0.0 && std::isfinite(out->mu) && std::isfinite(out->energy) && std::isfinite(out->rms_r);
+    return ok ? GP_OK : GP_ERR_NONFINITE;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, const double *dt,
+                          const double *traps, const double *g, gp_mode mode, gp_dtype dtype, int flags,
+                          void *hip_stream, gp_batch **out)
+{
+    if (!out) return fail(GP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nsolves < 1 || !grids || !dx || !dt || !traps || !g)
+        return fail(GP_ERR_INVALID, "need nsolves >= 1 and every parameter array");
+    if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
+    if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
+    if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE)) return fail(GP_ERR_INVALID, "unknown flags");
+    for (int i = 0; i < nsolves; ++i) {
+        if (!valid_grid(grids + 3 * i)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
+        for (int a = 0; a < 3; ++a) {
+            if (!finite_pos(dx[3 * i + a])) return fail(GP_ERR_INVALID, "dx must be finite and > 0");
+            if (!std::isfinite(traps[3 * i + a]) || traps[3 * i + a] < 0.0)
+                return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+        }
+        if (!finite_pos(dt[i])) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
+        if (!std::isfinite(g[i])) return fail(GP_ERR_INVALID, "g must be finite");
+        int c, l;
+        for (int a = 0; a < 3; ++a)
+            if (!sweep_shape(grids[3 * i + a], a, &c, &l, max_lanes_for(dtype)))
+                return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
+    }
+    gp_batch *b = new (std::nothrow) gp_batch();
+    if (!b) return fail(GP_ERR_NOMEM, "host allocation failed");
+    b->n = nsolves;
+    b->mode = mode;
+    b->dtype = dtype;
+    b->flags = flags;
+    b->caller = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        release(b);
+        return fail_hip(e, "creating the batch's stream");
+    }
+    const bool real = mode == GP_MODE_REAL;
+    // classes by grid shape
+    std::map<std::tuple<int64_t, int64_t, int64_t>, int> index;
+    b->s.resize((size_t)nsolves);
+    int64_t part = 0;
+    size_t tab_bytes = 0;
+    const size_t cs = dtype == GP_C64 ? sizeof(cx<float>) : sizeof(cx<double>);
+    for (int i = 0; i < nsolves; ++i) {
+        Solve &x = b->s[(size_t)i];
+        for (int a = 0; a < 3; ++a) {
+            x.grid[a] = grids[3 * i + a];
+            x.dx[a] = dx[3 * i + a];
+            x.omega[a] = traps[3 * i + a];
+        }
+        x.dt = dt[i];
+        x.g = g[i];
+        x.elems = x.grid[0] * x.grid[1] * x.grid[2];
+        auto key = std::make_tuple(x.grid[0], x.grid[1], x.grid[2]);
+        auto it = index.find(key);
+        if (it == index.end()) {
+            Class c;
+            for (int a = 0; a < 3; ++a) {
+                c.grid[a] = x.grid[a];
+                sweep_shape(x.grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype));
+            }
+            c.xt_y = strided_columns(c.grid[0], c.lanes[1]);
+            c.xt_z = strided_columns(c.grid[0], c.lanes[2]);
+            class_shapes(c);
+            it = index.emplace(key, (int)b->cls.size()).first;
+            b->cls.push_back(c);
+        }
+        x.cls = it->second;
+        Class &c = b->cls[(size_t)x.cls];
+        c.members.push_back(i);
+        for (int a = 0; a < 3; ++a) {
+            build_axis(x.grid[a], x.dx[a], x.dt, real, c.chunk[a], c.lanes[a], x.ax[a]);
+            x.zt_off[a] = (int64_t)tab_bytes;
+            tab_bytes += cs * (size_t)c.chunk[a] * (size_t)c.lanes[a];
+        }
+        x.part_off = part;
+        part += x.grid[0] * x.grid[1];
+    }
+    b->active.assign((size_t)nsolves, 1);
+    // tables
+    std::vector<unsigned char> tab(tab_bytes, 0);
+    for (const Solve &x : b->s) {
+        const size_t off3[3] = {(size_t)x.zt_off[0], (size_t)x.zt_off[1], (size_t)x.zt_off[2]};
+        for (int a = 0; a < 3; ++a) {
+            for (int64_t q = 0; q < x.grid[a]; ++q) {
+                if (dtype == GP_C64) {
+                    const cx<float> v = to_cx<float>(x.ax[a].zt[(size_t)q]);
+                    std::memcpy(&tab[off3[a] + (size_t)q * sizeof v], &v, sizeof v);
+                } else {
+                    const cx<double> v = to_cx<double>(x.ax[a].zt[(size_t)q]);
+                    std::memcpy(&tab[off3[a] + (size_t)q * sizeof v], &v, sizeof v);
+                }
+            }
+        }
+    }
+    int max_obs = 0;
+    for (const Class &c : b->cls) max_obs = std::max(max_obs, c.obs_blocks);
+#define GB_ALLOC(ptr, bytes)                                                          \
+    do {                                                                              \
+        e = hipMalloc((void **)&(ptr), (bytes));                                      \
+        if (e != hipSuccess) {                                                        \
+            (void)hipGetLastError();                                                  \
+            release(b);                                                               \
+            return e == hipErrorOutOfMemory ? fail(GP_ERR_NOMEM, "hipMalloc failed")  \
+                                            : fail_hip(e, "hipMalloc");               \
+        }                                                                             \
+    } while (0)
+    GB_ALLOC(b->d_tables, std::max<size_t>(tab_bytes, 16));
+    const size_t xs = dtype == GP_C64 ? sizeof(gpssc::XBatchArgs<float>) : sizeof(gpssc::XBatchArgs<double>);
+    const size_t ss = dtype == GP_C64 ? sizeof(gpssc::SBatchArgs<float>) : sizeof(gpssc::SBatchArgs<double>);
+    GB_ALLOC(b->d_xargs, xs * (size_t)nsolves);
+    GB_ALLOC(b->d_yargs, ss * (size_t)nsolves);
+    GB_ALLOC(b->d_zargs, ss * (size_t)nsolves);
+    GB_ALLOC(b->d_psis, sizeof(void *) * (size_t)nsolves);
+    GB_ALLOC(b->d_partials, sizeof(double) * (size_t)std::max<int64_t>(part, 1));
+    GB_ALLOC(b->d_part_off, sizeof(int64_t) * (size_t)nsolves);
+    GB_ALLOC(b->d_dv, sizeof(double) * (size_t)nsolves);
+    GB_ALLOC(b->d_scales, sizeof(double) * (size_t)nsolves);
+    GB_ALLOC(b->d_flags, sizeof(int) * (size_t)nsolves);
+    GB_ALLOC(b->d_obsargs, sizeof(gpssc::ObsArgs<double>) * (size_t)nsolves);
+    GB_ALLOC(b->d_obs_partials, sizeof(double) * gpssc::OBS_NSUMS * (size_t)max_obs * (size_t)nsolves);
+    GB_ALLOC(b->d_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)nsolves);
+    for (Class &c : b->cls) GB_ALLOC(c.d_active, sizeof(int) * c.members.size());
+#undef GB_ALLOC
+    e = hipHostMalloc((void **)&b->h_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)nsolves, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_flags, sizeof(int) * (size_t)nsolves, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_psis, sizeof(void *) * (size_t)nsolves, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_active, sizeof(int) * (size_t)nsolves, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(b);
+        return fail_hip(e, "hipHostMalloc");
+    }
+    // per-solve constants
+    std::vector<int64_t> offs((size_t)nsolves);
+    std::vector<double> dvs((size_t)nsolves), ones((size_t)nsolves, 1.0);
+    std::vector<int> zeros((size_t)nsolves, 0);
+    std::vector<gpssc::ObsArgs<double>> oa((size_t)nsolves);
+    for (int i = 0; i < nsolves; ++i) {
+        const Solve &x = b->s[(size_t)i];
+        offs[(size_t)i] = x.part_off;
+        dvs[(size_t)i] = x.dx[0] * x.dx[1] * x.dx[2];
+        gpssc::ObsArgs<double> &o = oa[(size_t)i];
+        o.nx = (int)x.grid[0];
+        o.ny = (int)x.grid[1];
+        o.nz = (int)x.grid[2];
+        o.c0x = 0.5 * (double)(x.grid[0] - 1);
+        o.c0y = 0.5 * (double)(x.grid[1] - 1);
+        o.c0z = 0.5 * (double)(x.grid[2] - 1);
+        o.dx = x.dx[0];
+        o.dy = x.dx[1];
+        o.dz = x.dx[2];
+        o.hgx = 0.5 * x.omega[0] * x.omega[0];
+        o.hgy = 0.5 * x.omega[1] * x.omega[1];
+        o.hgz = 0.5 * x.omega[2] * x.omega[2];
+    }
+    std::vector<unsigned char> xa = dtype == GP_C64 ? pack_batch_args<float>(b, 0) : pack_batch_args<double>(b, 0);
+    std::vector<unsigned char> ya = dtype == GP_C64 ? pack_batch_args<float>(b, 1) : pack_batch_args<double>(b, 1);
+    std::vector<unsigned char> za = dtype == GP_C64 ? pack_batch_args<float>(b, 2) : pack_batch_args<double>(b, 2);
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t n;
+    } ups[] = {
+        {b->d_tables, tab.data(), tab.size()},
+        {b->d_xargs, xa.data(), xa.size()},
+        {b->d_yargs, ya.data(), ya.size()},
+        {b->d_zargs, za.data(), za.size()},
+        {b->d_part_off, offs.data(), sizeof(int64_t) * offs.size()},
+        {b->d_dv, dvs.data(), sizeof(double) * dvs.size()},
+        {b->d_scales, ones.data(), sizeof(double) * ones.size()},
+        {b->d_flags, zeros.data(), sizeof(int) * zeros.size()},
+        {b->d_obsargs, oa.data(), sizeof(gpssc::ObsArgs<double>) * oa.size()},
+    };
+    for (const Up &u : ups)
+        if (e == hipSuccess && u.n) e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    if (e == hipSuccess && (flags & GP_BATCH_TUNE)) {
+        for (Class &c : b->cls) {
+            e = dtype == GP_C128 ? tune_class<double2>(b, c) : tune_class<float2>(b, c);
+            if (e != hipSuccess) break;
+            class_shapes(c);
+        }
+        // the tuned shapes change the per-solve y/z arguments only through
+        // the block shape, which the kernels read from blockDim
+    }
+    if (e == hipSuccess) e = upload_active(b);
+    if (e != hipSuccess) {
+        release(b);
+        return fail_hip(e, "setting up the batch");
+    }
+    *out = b;
+    return GP_OK;
+}
+
+gp_status gp_batch_destroy(gp_batch *b)
+{
+    if (!b) return GP_OK;
+    DeviceGuard guard(b->device);
+    hipStreamSynchronize(b->own);
+    release(b);
+    return GP_OK;
+}
+
+gp_status gp_batch_set_psi(gp_batch *b, void *const *psi, const int64_t *elems)
+{
+    if (!b) return fail(GP_ERR_INVALID, "batch is NULL");
+    if (!psi || !elems) return fail(GP_ERR_INVALID, "psi and elems arrays are required");
+    DeviceGuard guard(b->device);
+    const uintptr_t align = b->dtype == GP_C128 ? 16 : 8;
+    for (int i = 0; i < b->n; ++i) {
+        if (!psi[i]) return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] is NULL");
+        if (elems[i] != b->s[(size_t)i].elems)
+            return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] holds " + std::to_string(elems[i]) +
+                                            " elements, its grid needs " + std::to_string(b->s[(size_t)i].elems));
+        if ((uintptr_t)psi[i] % align) return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] is misaligned");
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, psi[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] is not a device pointer");
+        }
+        if ((attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) || attr.device != b->device)
+            return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] is not device memory of the batch's device");
+    }
+    hipError_t e = sync_in(b);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);   // the staging below is reused
+    for (int i = 0; i < b->n; ++i) {
+        b->s[(size_t)i].psi = psi[i];
+        b->h_psis[i] = psi[i];
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_psis, b->h_psis, sizeof(void *) * (size_t)b->n, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    if (e != hipSuccess) return fail_hip(e, "binding psi");
+    return GP_OK;
+}
+
+gp_status gp_batch_set_active(gp_batch *b, const unsigned char *mask)
+{
+    if (!b) return fail(GP_ERR_INVALID, "batch is NULL");
+    DeviceGuard guard(b->device);
+    hipError_t e = hipStreamSynchronize(b->own);
+    if (e != hipSuccess) return fail_hip(e, "synchronising the batch");
+    for (int i = 0; i < b->n; ++i) b->active[(size_t)i] = mask ? (mask[i] ? 1 : 0) : 1;
+    e = upload_active(b);
+    if (e != hipSuccess) return fail_hip(e, "uploading the active lists");
+    b->graph_ok = false;
+    return GP_OK;
+}
+
+gp_status gp_batch_step(gp_batch *b, int64_t nsteps)
+{
+    if (!b) return fail(GP_ERR_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(GP_ERR_INVALID, "nsteps must be >= 0");
+    if (!bound(b)) return fail(GP_ERR_INVALID, "bind psi with gp_batch_set_psi first");
+    if (nsteps == 0) return GP_OK;
+    DeviceGuard guard(b->device);
+    hipError_t e = sync_in(b);
+    const bool use_graph = (b->flags & GP_BATCH_GRAPH) != 0;
+    if (e == hipSuccess && use_graph && !b->graph_ok) e = build_graph(b);
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
+        e = use_graph ? hipGraphLaunch(b->exec, b->own) : enqueue_step(b);
+    if (e == hipSuccess && b->mode == GP_MODE_IMAG) {
+        const bool c64 = b->dtype != GP_C128;
+        for (const Class &c : b->cls) {
+            if (!c.nact) continue;
+            e = gpssc::launch_scale_batch(c64, c.nact, c.d_active, b->d_psis, c.grid[0] * c.grid[1] * c.grid[2],
+                                          b->d_scales, b->own);
+            if (e != hipSuccess) break;
+        }
+    }
+    if (e == hipSuccess) e = sync_out(b);
+    if (e != hipSuccess) return fail_hip(e, "queueing batch steps");
+    b->steps_done += nsteps;
+    return GP_OK;
+}
+
+gp_status gp_batch_observables(gp_batch *b, gp_obs *out)
+{
+    if (!b || !out) return fail(GP_ERR_INVALID, "batch and out are required");
+    if (!bound(b)) return fail(GP_ERR_INVALID, "bind psi with gp_batch_set_psi first");
+    DeviceGuard guard(b->device);
+    hipError_t e = sync_in(b);
+    const bool c64 = b->dtype != GP_C128;
+    for (const Class &c : b->cls) {
+        if (!c.nact || e != hipSuccess) continue;
+        e = gpssc::launch_observables_batch(c64, c.nact, c.d_active, b->d_psis, b->d_obsargs, (int)c.grid[0],
+                                            (int)c.grid[1], b->d_obs_partials, b->d_sums, b->own);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_sums, b->d_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)b->n,
+                           hipMemcpyDeviceToHost, b->own);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int) * (size_t)b->n, hipMemcpyDeviceToHost, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    if (e == hipSuccess) e = sync_out(b);
+    if (e != hipSuccess) return fail_hip(e, "computing batch observables");
+    bool flagged = false;
+    for (int i = 0; i < b->n; ++i) flagged = flagged || b->h_flags[i] != 0;
+    if (flagged) {   // report once, then clear
+        std::vector<int> zeros((size_t)b->n, 0);
+        e = hipMemcpyAsync(b->d_flags, zeros.data(), sizeof(int) * zeros.size(), hipMemcpyHostToDevice, b->own);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+        if (e != hipSuccess) return fail_hip(e, "clearing the batch's error flags");
+    }
+    gp_status worst = GP_OK;
+    for (int i = 0; i < b->n; ++i) {
+        if (!b->active[(size_t)i]) continue;
+        gp_status st = obs_from_sums(b->h_sums + (size_t)i * gpssc::OBS_NSUMS, b->s[(size_t)i], &out[i],
+                                     b->steps_done);
+        if (b->h_flags[i]) st = GP_ERR_NONFINITE;
+        if (st != GP_OK) worst = st;
+    }
+    if (worst != GP_OK) return fail(worst, "a solve has a zero or non-finite norm or observable");
+    return GP_OK;
+}
+
+gp_status gp_batch_solve_imag(gp_batch *b, double tol, int64_t check_every, int64_t max_steps, gp_obs *out,
+                              int64_t *steps, unsigned char *converged)
+{
+    if (!b || !out || !steps || !converged) return fail(GP_ERR_INVALID, "batch and output arrays are required");
+    if (b->mode != GP_MODE_IMAG) return fail(GP_ERR_INVALID, "gp_batch_solve_imag needs an imaginary-time batch");
+    if (!(tol > 0.0) || check_every < 1 || max_steps < 1)
+        return fail(GP_ERR_INVALID, "need tol > 0, check_every >= 1, max_steps >= 1");
+    std::vector<unsigned char> act((size_t)b->n, 1);
+    std::vector<double> last((size_t)b->n, NAN);
+    for (int i = 0; i < b->n; ++i) {
+        steps[i] = 0;
+        converged[i] = 0;
+    }
+    gp_status st = gp_batch_set_active(b, act.data());
+    if (st != GP_OK) return st;
+    st = gp_batch_observables(b, out);
+    if (st != GP_OK) return st;
+    for (int i = 0; i < b->n; ++i) last[(size_t)i] = out[i].mu;
+    int64_t done = 0;
+    int left = b->n;
+    while (left > 0 && done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        st = gp_batch_step(b, k);
+        if (st == GP_OK) st = gp_batch_observables(b, out);
+        if (st != GP_OK) return st;
+        done += k;
+        bool changed = false;
+        for (int i = 0; i < b->n; ++i) {
+            if (!act[(size_t)i]) continue;
+            steps[i] = done;
+            if (std::fabs(out[i].mu - last[(size_t)i]) < tol) {
+                converged[i] = 1;
+                act[(size_t)i] = 0;
+                --left;
+                changed = true;
+            }
+            last[(size_t)i] = out[i].mu;
+        }
+        if (changed && left > 0) {
+            st = gp_batch_set_active(b, act.data());
+            if (st != GP_OK) return st;
+        }
+    }
+    // leave every solve active again
+    return gp_batch_set_active(b, nullptr);
+}
+
+gp_status gp_batch_describe(const gp_batch *b, char *buf, size_t len)
+{
+    if (!b || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_batch_describe arguments");
+    std::string d = std::to_string(b->n) + " solves, " + std::to_string(b->cls.size()) + " classes";
+    for (const Class &c : b->cls) {
+        char t[200];
+        std::snprintf(t, sizeof t, " | %lldx%lldx%lld: %zu solves, x chunk %d, y chunk %d x %d (%d cols), z chunk %d x %d (%d cols)",
+                      (long long)c.grid[0], (long long)c.grid[1], (long long)c.grid[2], c.members.size(), c.chunk[0],
+                      c.chunk[1], c.lanes[1], c.xt_y, c.chunk[2], c.lanes[2], c.xt_z);
+        d += t;
+    }
+    std::snprintf(buf, len, "%s", d.c_str());
+    return GP_OK;
+}
+
+}  // extern "C"

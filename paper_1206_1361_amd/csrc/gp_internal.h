@@ -145,6 +145,19 @@ struct SArgs {
     SweepCoef<A> k;
 };
 
+// Per-solve arguments of the batched kernels (device arrays indexed by solve).
+template <typename A>
+struct XBatchArgs {
+    XArgs<A> x;
+    const cx<A> *zt;       // this solve's x correction
+};
+
+template <typename A>
+struct SBatchArgs {
+    SArgs<A> s;
+    const cx<A> *zt;       // this solve's y or z correction
+};
+
 // Sums of the observables pass, FP64.
 enum {
     OBS_DENS = 0, OBS_POT, OBS_QUART,
@@ -176,8 +189,8 @@ hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, 
 
 // calcluy / calcluz over ceil(nx/xt) x nouter tiles.  nblocks: blocks to
 // launch (each loops over tiles; 0 or >= the tile count = one per tile).
-// zt: boundary correction by position.  partials: NULL, or one double per
-// tile (sum |psi|^2 of the tile's output).
+// zt: boundary correction by position.  partials: NULL, or nx * nouter
+// doubles: sum |psi|^2 of each line's output, at outer * nx + column.
 hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, int nblocks,
                           void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream);
@@ -196,5 +209,34 @@ hipError_t launch_scale(bool c64, void *psi, int64_t elems, const double *scale,
 int obs_num_blocks(int nx, int ny);
 hipError_t launch_observables(bool c64, const void *psi, const ObsArgs<double> &args,
                               double *partials, double *sums, hipStream_t stream);
+
+// ---- batched launchers: one launch covers every active solve of one grid
+// shape.  psis[i], args[i]: solve i's psi and arguments (device arrays);
+// active[0..nact): the solves to advance. ----
+
+hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlines, void *const *psis,
+                             const void *args, const int *active, const double *scales,
+                             hipStream_t stream);
+
+// partials + part_off[i]: solve i's per-line norm partials (NULL: none).
+hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lanes, int nact,
+                                int ncol, int ntiles, void *const *psis, const void *args,
+                                const int *active, double *partials, const int64_t *part_off,
+                                hipStream_t stream);
+
+// Per solve: 1/sqrt(dv_i * sum of its npart partials) -> scales[i]; flags[i]
+// raised for a non-finite or zero norm.
+hipError_t launch_norm_finalize_batch(int nact, const int *active, const double *partials,
+                                      const int64_t *part_off, int npart, const double *dv,
+                                      double *scales, int *flags, hipStream_t stream);
+
+// psi_i <- psi_i * scales[i] for the active solves, then scales[i] <- 1.
+hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const *psis,
+                              int64_t elems, double *scales, hipStream_t stream);
+
+// Observables sums per solve: sums[i * OBS_NSUMS + q].
+hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
+                                    const ObsArgs<double> *args, int nx, int ny, double *partials,
+                                    double *sums, hipStream_t stream);
 
 }  // namespace gpssc

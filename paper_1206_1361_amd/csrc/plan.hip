@@ -19,207 +19,19 @@
 #include <vector>
 
 #include "gp_internal.h"
+#include "host_common.h"
 
-using gpssc::cx;
-using cplx = std::complex<double>;
+namespace gpssc_host {
+thread_local std::string g_last_error;
+}  // namespace gpssc_host
+
+using namespace gpssc_host;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-gp_status fail(gp_status s, const std::string &msg)
-{
-    g_last_error = msg;
-    return s;
-}
-
-gp_status fail_hip(hipError_t e, const char *what)
-{
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-    return GP_ERR_DEVICE;
-}
-
-const int kChunksX[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
-const int kChunksYZ[] = {1, 2, 4, 8, 16};
-
-int max_lanes_for(gp_dtype dtype) { return dtype == GP_C64 ? 32 : gpssc::kMaxLanesYZ; }
-
-// Chunking of a line of n points along `axis`: chunk points per lane, lanes
-// per line.  Returns false when the line is longer than the kernels handle.
-// y/z: the fewest points per thread that keep the chunks of a line within
-// max_lanes; FP32 arithmetic affords 16-point chunks at 32 chunks per line
-// (fewer scan stages, wider blocks), FP64 keeps 64 chunks of at most 8
-// points for lines up to 512 so two 1024-thread blocks fit on a compute unit.
-bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes, int max_lanes = gpssc::kMaxLanesYZ)
-{
-    if (n < 1) return false;
-    if (axis == 0) {
-        for (int c : kChunksX)
-            if ((int64_t)c * gpssc::kWave >= n) {
-                *chunk = c;
-                *lanes = gpssc::kWave;
-                return true;
-            }
-        return false;
-    }
-    for (int c : kChunksYZ) {
-        const int64_t p = (n + c - 1) / c;
-        if (p <= max_lanes || (c == kChunksYZ[4] && p <= gpssc::kMaxLanesYZ)) {
-            *chunk = c;
-            *lanes = (int)p;
-            return true;
-        }
-    }
-    return false;
-}
-
-// Columns per y/z block: as wide as 64 (one full wavefront of contiguous
-// x), narrowed so the block holds at most 1024 threads and not far wider
-// than the grid.
-#ifndef GPSSC_YZ_COLS
-#define GPSSC_YZ_COLS 64
-#endif
-
-int strided_columns(int64_t nx, int lanes)
-{
-    int xt = GPSSC_YZ_COLS;
-    while (xt * lanes > gpssc::kMaxBlockYZ) xt /= 2;
-    while (xt > 16 && xt / 2 >= nx) xt /= 2;
-    return xt;
-}
-
-// Constant coefficients of one axis, FP64.  Crank-Nicolson along the axis:
-// (1 + tau/2 T) psi' = (1 - tau/2 T) psi, T psi_i = -(psi_{i+1} - 2 psi_i +
-// psi_{i-1})/(2 dx^2), tau = dt or i dt.  With kappa = tau/(2 dx^2) the left
-// matrix is tridiag(o, b, o), b = 1 + kappa, o = -kappa/2, and the right side
-// is (1 - kappa) psi_i + kappa/2 (psi_{i-1} + psi_{i+1}).
-struct AxisTables {
-    int64_t n = 0;
-    int chunk = 0, lanes = 0;
-    cplx kappa, b, o;
-    cplx c, beta, m, a;          // A = beta (I + c S)(I + c S^T) + beta c^2 e0 e0^T; m = 1/beta, a = -c
-    std::vector<cplx> zt;        // boundary correction x = y + y_0 zt, by position
-    cplx stage[gpssc::kMaxStages];  // a^(chunk 2^s)
-};
-
-// The factorisation: c is the root of o c^2 - b c + o = 0 inside the unit
-// circle (the two roots multiply to 1), taken as 2o / (b + sqrt(b^2 - 4o^2))
-// with the square root that makes |c| < 1, so nothing cancels.  beta = o/c,
-// so beta (1 + c^2) = b and beta c = o.
-void build_axis(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t)
-{
-    const cplx tau = real ? cplx(0.0, dt) : cplx(dt, 0.0);
-    t.n = n;
-    t.chunk = chunk;
-    t.lanes = lanes;
-    t.kappa = tau / (2.0 * dx * dx);
-    t.b = 1.0 + t.kappa;
-    t.o = -0.5 * t.kappa;
-    const cplx disc = std::sqrt(t.b * t.b - 4.0 * t.o * t.o);
-    const cplx den = std::abs(t.b + disc) >= std::abs(t.b - disc) ? t.b + disc : t.b - disc;
-    t.c = 2.0 * t.o / den;
-    t.beta = t.o / t.c;
-    t.m = 1.0 / t.beta;
-    t.a = -t.c;
-    // z = M^-1 e_0 for M = beta (I + c S)(I + c S^T): forward w_i = a^i / beta,
-    // then back substitution y_i = w_i + a y_{i+1} from the last node.
-    std::vector<cplx> w((size_t)n), z((size_t)n);
-    w[0] = t.m;
-    for (int64_t i = 1; i < n; ++i) w[(size_t)i] = t.a * w[(size_t)i - 1];
-    z[(size_t)n - 1] = w[(size_t)n - 1];
-    for (int64_t i = n - 2; i >= 0; --i) z[(size_t)i] = w[(size_t)i] + t.a * z[(size_t)i + 1];
-    // A = M + u e_0^T, u = beta c^2 e_0:  x = y - (beta c^2 y_0 / (1 + beta c^2 z_0)) z
-    const cplx bc2 = t.beta * t.c * t.c;
-    const cplx gam = -bc2 / (1.0 + bc2 * z[0]);
-    t.zt.resize((size_t)n);
-    for (int64_t i = 0; i < n; ++i) t.zt[(size_t)i] = gam * z[(size_t)i];
-    cplx p(1.0, 0.0);
-    for (int q = 0; q < chunk; ++q) p *= t.a;
-    for (int s = 0; s < gpssc::kMaxStages; ++s) {
-        t.stage[s] = p;
-        p *= p;
-    }
-}
-
-template <typename A>
-cx<A> to_cx(cplx v) { return cx<A>{(A)v.real(), (A)v.imag()}; }
-
-template <typename A>
-bool is_zero(cplx v) { return (A)v.real() == (A)0 && (A)v.imag() == (A)0; }
-
-// Coefficients of one axis in the arithmetic type.  Stages whose multiplier
-// rounds to zero are dropped (every later one is zero too: it is the square
-// of the previous); stages that would reach past the last lane are dropped
-// because no lane has a partner there.  The correction is kept up to its last
-// position that does not round to zero.
-template <typename A>
-gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, double dt, double dx)
-{
-    gpssc::SweepCoef<A> k;
-    k.kap = (A)(dt / (2.0 * dx * dx));
-    k.m = to_cx<A>(t.m);
-    k.a = to_cx<A>(t.a);
-    k.nst = 0;
-    for (int s = 0; s < gpssc::kMaxStages; ++s) {
-        k.stage[s] = to_cx<A>(t.stage[s]);
-        if ((1 << s) < t.lanes && !is_zero<A>(t.stage[s]) && k.nst == s) k.nst = s + 1;
-    }
-    int nz = (int)t.n;
-    while (nz > 0 && is_zero<A>(t.zt[(size_t)nz - 1])) --nz;
-    k.nzc = nz;
-    return k;
-}
-
-// Device image of the correction vectors of the three axes, in the
-// arithmetic type, each padded to chunk * lanes positions.
-template <typename A>
-std::vector<unsigned char> pack_tables(const AxisTables ax[3], size_t off[3])
-{
-    std::vector<cx<A>> v;
-    for (int a = 0; a < 3; ++a) {
-        off[a] = v.size();
-        for (const cplx &z : ax[a].zt) v.push_back(to_cx<A>(z));
-        const size_t npad = (size_t)ax[a].chunk * ax[a].lanes;
-        while (v.size() - off[a] < npad) v.push_back(cx<A>{0, 0});
-    }
-    std::vector<unsigned char> bytes(v.size() * sizeof(cx<A>));
-    std::memcpy(bytes.data(), v.data(), bytes.size());
-    for (int q = 0; q < 3; ++q) off[q] *= sizeof(cx<A>);
-    return bytes;
-}
 
 struct ProfRec {
     int cls;
     hipEvent_t a, b;
-};
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-bool valid_dtype(gp_dtype d) { return d == GP_C128 || d == GP_C64 || d == GP_C64_F64; }
-
-bool valid_grid(const int64_t grid[3])
-{
-    if (!grid) return false;
-    for (int a = 0; a < 3; ++a)
-        if (grid[a] < 1) return false;
-    return true;
-}
-
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-        if (prev_ != dev) hipSetDevice(dev);
-        dev_ = dev;
-    }
-    ~DeviceGuard()
-    {
-        if (prev_ >= 0 && prev_ != dev_) hipSetDevice(prev_);
-    }
-
-  private:
-    int prev_ = -1, dev_ = 0;
 };
 
 }  // namespace
@@ -239,7 +51,7 @@ struct gp_plan {
 
     unsigned char *d_tables = nullptr;
     size_t tab_off[3];
-    double *d_partials = nullptr;   // z-sweep norm partials
+    double *d_partials = nullptr;   // z-sweep norm partials, one per z line
     int n_zblocks = 0;
     double *d_obs_partials = nullptr;
     int n_obs_blocks = 0;
@@ -330,7 +142,7 @@ size_t footprint(const int64_t grid[3], gp_dtype dtype, int *xt_y, int *xt_z)
     const int xz = strided_columns(grid[0], l[2]);
     if (xt_y) *xt_y = xy;
     if (xt_z) *xt_z = xz;
-    const size_t zblocks = (size_t)((grid[0] + xz - 1) / xz) * (size_t)grid[1];
+    const size_t zblocks = (size_t)grid[0] * (size_t)grid[1];   // norm partials, one per z line
     const size_t oblocks = (size_t)gpssc::obs_num_blocks((int)grid[0], (int)grid[1]);
     return tab + zblocks * 8 + oblocks * gpssc::OBS_NSUMS * 8 + 8 + 8 + gpssc::OBS_NSUMS * 8;
 }
@@ -571,7 +383,7 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     footprint(grid, dtype, &p->xt_y, &p->xt_z);
     std::vector<unsigned char> tab = dtype == GP_C64 ? pack_tables<float>(p->ax, p->tab_off)
                                                      : pack_tables<double>(p->ax, p->tab_off);
-    p->n_zblocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
+    p->n_zblocks = (int)(grid[0] * grid[1]);   // one norm partial per z line
     p->n_obs_blocks = gpssc::obs_num_blocks((int)grid[0], (int)grid[1]);
 
 #define GP_ALLOC(ptr, bytes)                                                    \

@@ -44,6 +44,53 @@ calcnorm_finalize_kernel(const double *__restrict__ partials, int n, double dv,
     }
 }
 
+// Batched: block b finalises solve active[b].
+__global__ void __launch_bounds__(kReduceThreads)
+calcnorm_finalize_batch_kernel(const int *__restrict__ active, const double *__restrict__ partials,
+                               const int64_t *__restrict__ part_off, int ntiles,
+                               const double *__restrict__ dv, double *__restrict__ scales,
+                               int *__restrict__ flags)
+{
+    __shared__ double red[kReduceThreads];
+    const int si = active[blockIdx.x];
+    const double *p = partials + part_off[si];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < ntiles; b += kReduceThreads) acc += p[b];
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        const double norm = dv[si] * sum;
+        const bool ok = norm > 0.0 && isfinite(norm);
+        scales[si] = ok ? 1.0 / sqrt(norm) : (double)NAN;
+        if (!ok) flags[si] = 1;
+    }
+}
+
+// Batched: blockIdx.y picks the solve; afterwards its scale is reset to 1 by
+// reset_scales_kernel (a separate launch, once every block has read it).
+template <typename S>
+__global__ void __launch_bounds__(kReduceThreads)
+scale_batch_kernel(S *const *__restrict__ psis, const int *__restrict__ active, int64_t elems,
+                   const double *__restrict__ scales)
+{
+    using R = typename storage_traits<S>::real;
+    const int si = active[blockIdx.y];
+    const R s = (R)scales[si];
+    S *psi = psis[si];
+    const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
+    for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
+        S v = psi[p];
+        v.x *= s;
+        v.y *= s;
+        psi[p] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+reset_scales_kernel(const int *__restrict__ active, int nact, double *__restrict__ scales)
+{
+    for (int b = threadIdx.x; b < nact; b += kReduceThreads) scales[active[b]] = 1.0;
+}
+
 template <typename S>
 __global__ void __launch_bounds__(kReduceThreads)
 scale_kernel(S *__restrict__ psi, int64_t elems, const double *__restrict__ scale)
@@ -67,14 +114,12 @@ scale_kernel(S *__restrict__ psi, int64_t elems, const double *__restrict__ scal
 constexpr int kObsX = 64, kObsY = 4;
 
 template <typename S>
-__global__ void __launch_bounds__(kObsX * kObsY)
-calcmuen_rms_kernel(const S *__restrict__ psi, const ObsArgs<double> a,
-                    double *__restrict__ partials)
+__device__ __forceinline__ void obs_block(const S *__restrict__ psi, const ObsArgs<double> &a,
+                                          double *__restrict__ out, double *red, int bx, int by)
 {
-    __shared__ double red[kReduceThreads];
     const int tx = threadIdx.x % kObsX, ty = threadIdx.x / kObsX;
-    const int i = blockIdx.x * kObsX + tx;
-    const int j = blockIdx.y * kObsY + ty;
+    const int i = bx * kObsX + tx;
+    const int j = by * kObsY + ty;
     double acc[OBS_NSUMS];
 #pragma unroll
     for (int q = 0; q < OBS_NSUMS; ++q) acc[q] = 0.0;
@@ -127,12 +172,36 @@ calcmuen_rms_kernel(const S *__restrict__ psi, const ObsArgs<double> a,
         acc[OBS_LINKZ] += prev_re * prev_re + prev_im * prev_im;  // ghost beyond the last node
     }
 
-    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int q = 0; q < OBS_NSUMS; ++q) {
         const double s = block_sum(acc[q], red);
-        if (threadIdx.x == 0) partials[b * OBS_NSUMS + q] = s;
+        if (threadIdx.x == 0) out[q] = s;
     }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kObsX * kObsY)
+calcmuen_rms_kernel(const S *__restrict__ psi, const ObsArgs<double> a,
+                    double *__restrict__ partials)
+{
+    __shared__ double red[kReduceThreads];
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    obs_block(psi, a, partials + b * OBS_NSUMS, red, blockIdx.x, blockIdx.y);
+}
+
+// Batched: blockIdx.z picks the solve; its partials start at
+// partials + solve * (gridDim.x * gridDim.y) * OBS_NSUMS.
+template <typename S>
+__global__ void __launch_bounds__(kObsX * kObsY)
+calcmuen_rms_batch_kernel(S *const *__restrict__ psis, const int *__restrict__ active,
+                          const ObsArgs<double> *__restrict__ args, double *__restrict__ partials)
+{
+    __shared__ double red[kReduceThreads];
+    const int si = active[blockIdx.z];
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    obs_block<S>(psis[si], args[si], partials + ((int64_t)si * nb + b) * OBS_NSUMS, red, blockIdx.x,
+                 blockIdx.y);
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -146,6 +215,73 @@ obs_finalize_kernel(const double *__restrict__ partials, int nblocks, double *__
         const double s = block_sum(acc, red);
         if (threadIdx.x == 0) sums[q] = s;
     }
+}
+
+// Batched: block b sums solve active[b]'s partials into sums[si].
+__global__ void __launch_bounds__(kReduceThreads)
+obs_finalize_batch_kernel(const int *__restrict__ active, const double *__restrict__ partials,
+                          int nblocks, double *__restrict__ sums)
+{
+    __shared__ double red[kReduceThreads];
+    const int si = active[blockIdx.x];
+    const double *p = partials + (int64_t)si * nblocks * OBS_NSUMS;
+    for (int q = 0; q < OBS_NSUMS; ++q) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kReduceThreads) acc += p[(int64_t)b * OBS_NSUMS + q];
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) sums[(int64_t)si * OBS_NSUMS + q] = s;
+    }
+}
+
+hipError_t launch_norm_finalize_batch(int nact, const int *active, const double *partials,
+                                      const int64_t *part_off, int ntiles, const double *dv,
+                                      double *scales, int *flags, hipStream_t stream)
+{
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(calcnorm_finalize_batch_kernel, dim3((unsigned)nact), dim3(kReduceThreads), 0,
+                       stream, active, partials, part_off, ntiles, dv, scales, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const *psis, int64_t elems,
+                              double *scales, hipStream_t stream)
+{
+    if (nact <= 0) return hipSuccess;
+    int64_t blocks = (elems + kReduceThreads - 1) / kReduceThreads;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    const dim3 grid((unsigned)blocks, (unsigned)nact);
+    if (c64)
+        hipLaunchKernelGGL(scale_batch_kernel<float2>, grid, dim3(kReduceThreads), 0, stream,
+                           reinterpret_cast<float2 *const *>(psis), active, elems, scales);
+    else
+        hipLaunchKernelGGL(scale_batch_kernel<double2>, grid, dim3(kReduceThreads), 0, stream,
+                           reinterpret_cast<double2 *const *>(psis), active, elems, scales);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_scales_kernel, dim3(1), dim3(kReduceThreads), 0, stream, active, nact, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
+                                    const ObsArgs<double> *args, int nx, int ny, double *partials,
+                                    double *sums, hipStream_t stream)
+{
+    if (nact <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((nx + kObsX - 1) / kObsX), (unsigned)((ny + kObsY - 1) / kObsY),
+                    (unsigned)nact);
+    const dim3 block(kObsX * kObsY);
+    if (c64)
+        hipLaunchKernelGGL(calcmuen_rms_batch_kernel<float2>, grid, block, 0, stream,
+                           reinterpret_cast<float2 *const *>(psis), active, args, partials);
+    else
+        hipLaunchKernelGGL(calcmuen_rms_batch_kernel<double2>, grid, block, 0, stream,
+                           reinterpret_cast<double2 *const *>(psis), active, args, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(obs_finalize_batch_kernel, dim3((unsigned)nact), dim3(kReduceThreads), 0, stream,
+                       active, partials, (int)(grid.x * grid.y), sums);
+    return hipGetLastError();
 }
 
 hipError_t launch_norm_finalize(const double *partials, int n, double dv, double *scale,

@@ -155,6 +155,71 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
     }
 }
 
+// Batched: block b advances line b % nlines of solve active[b / nlines].
+template <typename S, typename A, int C, bool REAL>
+__global__ void __launch_bounds__(kWave)
+calcnu_lux_batch_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
+                        const int *__restrict__ active, int nlines, const double *__restrict__ scales)
+{
+    __shared__ S buf[kWave * C + kWave];
+    const int lane = threadIdx.x;
+    const int slot = blockIdx.x / nlines;
+    const int line = blockIdx.x - slot * nlines;
+    const int si = active[slot];
+    const XArgs<A> &a = args[si].x;
+    const A s = scales ? (A)scales[si] : (A)1;
+    S *row = psis[si] + (int64_t)line * a.nx;
+    S v[C];
+    load_x_row(v, row, a.nx);
+    solve_x_line<S, A, C, REAL>(v, buf, a, args[si].zt, s, line);
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+        const int e = r * kWave + lane;
+        if (e < a.nx) stream_store(row + e, v[r]);
+    }
+}
+
+template <typename S, typename A, bool REAL>
+static hipError_t launch_batch_c(int chunk, int nact, int nlines, void *const *psis, const void *args,
+                                 const int *active, const double *scales, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((int64_t)nact * nlines));
+    const dim3 block(kWave);
+    S *const *p = reinterpret_cast<S *const *>(psis);
+    const XBatchArgs<A> *a = static_cast<const XBatchArgs<A> *>(args);
+#define GP_XB_CASE(CC)                                                                        \
+    case CC:                                                                                  \
+        hipLaunchKernelGGL((calcnu_lux_batch_kernel<S, A, CC, REAL>), grid, block, 0, stream,  \
+                           p, a, active, nlines, scales);                                     \
+        break;
+    switch (chunk) {
+        GP_XB_CASE(1) GP_XB_CASE(2) GP_XB_CASE(3) GP_XB_CASE(4)
+        GP_XB_CASE(5) GP_XB_CASE(6) GP_XB_CASE(7) GP_XB_CASE(8)
+        GP_XB_CASE(10) GP_XB_CASE(12) GP_XB_CASE(14) GP_XB_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GP_XB_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlines, void *const *psis,
+                             const void *args, const int *active, const double *scales,
+                             hipStream_t stream)
+{
+    if (nact <= 0) return hipSuccess;
+#define GP_XB_PREC(S, A)                                                                      \
+    return real ? launch_batch_c<S, A, true>(chunk, nact, nlines, psis, args, active, scales, stream) \
+                : launch_batch_c<S, A, false>(chunk, nact, nlines, psis, args, active, scales, stream);
+    switch (prec) {
+    case PREC_C64: GP_XB_PREC(float2, float)
+    case PREC_C64_F64: GP_XB_PREC(float2, double)
+    case PREC_C128: GP_XB_PREC(double2, double)
+    }
+#undef GP_XB_PREC
+    return hipErrorInvalidValue;
+}
+
 template <typename S, typename A, bool REAL>
 static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, const void *zt,
                            const double *scale, hipStream_t stream)

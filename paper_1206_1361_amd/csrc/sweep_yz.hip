@@ -114,7 +114,9 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     }
 
     if (NORM) {
-        // sum |psi|^2 of what was stored (rounded to storage), fixed order
+        // sum |psi|^2 of what was stored (rounded to storage), one partial
+        // per line (column): over its chunks in order, so the sum does not
+        // depend on how many columns a block holds
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -123,21 +125,15 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
                 acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
             }
         }
-        // block sum by a fixed LDS tree (the block size need not be a
-        // multiple of the wavefront)
         __syncthreads();  // LDS reuse
         double *red = reinterpret_cast<double *>(smem_raw);
-        const int nthreads = XT * P;
-        int npow2 = 1;
-        while (npow2 < nthreads) npow2 <<= 1;
         red[me] = acc;
-        for (int idx = me + nthreads; idx < npow2; idx += nthreads) red[idx] = 0.0;
         __syncthreads();
-        for (int h = npow2 >> 1; h > 0; h >>= 1) {
-            if (me < h) red[me] += red[me + h];
-            __syncthreads();
+        if (pc == 0 && act) {
+            double col = 0.0;
+            for (int q = 0; q < P; ++q) col += red[q * XT + tx];
+            partials[(int64_t)outer * a.nx + i] = col;
         }
-        if (me == 0) partials[tile] = red[0];
     }
 }
 
@@ -156,6 +152,73 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
         solve_tile<S, A, C, REAL, NORM>(psi, a, zt, partials, smem_raw, tile, col0, outer);
         __syncthreads();  // LDS is free for the next tile
     }
+}
+
+// Batched: block b solves tile b % ntiles of solve active[b / ntiles].
+template <typename S, typename A, int C, bool REAL, bool NORM>
+__global__ void __launch_bounds__(kMaxBlockYZ)
+calclu_strided_batch_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__restrict__ args,
+                            const int *__restrict__ active, int ncol_tiles, int ntiles,
+                            double *__restrict__ partials, const int64_t *__restrict__ part_off)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int slot = blockIdx.x / ntiles;
+    const int tile = blockIdx.x - slot * ntiles;
+    const int si = active[slot];
+    const int outer = tile / ncol_tiles;
+    const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x;
+    solve_tile<S, A, C, REAL, NORM>(psis[si], args[si].s, args[si].zt,
+                                    NORM ? partials + part_off[si] : partials, smem_raw, tile, col0,
+                                    outer);
+}
+
+template <typename S, typename A, bool REAL>
+static hipError_t launch_batch_t(int chunk, int xt, int lanes, int nact, int ncol, int ntiles,
+                                 void *const *psis, const void *args, const int *active,
+                                 double *partials, const int64_t *part_off, hipStream_t stream)
+{
+    if (xt * lanes > kMaxBlockYZ || lanes > kMaxLanesYZ) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((int64_t)nact * ntiles));
+    const dim3 block((unsigned)xt, (unsigned)lanes);
+    const size_t lds = 2 * (size_t)xt * lanes * sizeof(cx<A>);
+    S *const *p = reinterpret_cast<S *const *>(psis);
+    const SBatchArgs<A> *a = static_cast<const SBatchArgs<A> *>(args);
+#define GP_SB_CASE(CC)                                                                                 \
+    case CC:                                                                                           \
+        if (partials)                                                                                  \
+            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, true>), grid, block, lds,   \
+                               stream, p, a, active, ncol, ntiles, partials, part_off);                \
+        else                                                                                           \
+            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, false>), grid, block, lds,  \
+                               stream, p, a, active, ncol, ntiles, partials, part_off);                \
+        break;
+    switch (chunk) {
+        GP_SB_CASE(1) GP_SB_CASE(2) GP_SB_CASE(4) GP_SB_CASE(8) GP_SB_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GP_SB_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lanes, int nact,
+                                int ncol, int ntiles, void *const *psis, const void *args,
+                                const int *active, double *partials, const int64_t *part_off,
+                                hipStream_t stream)
+{
+    if (nact <= 0) return hipSuccess;
+#define GP_SB_PREC(S, A)                                                                              \
+    return real ? launch_batch_t<S, A, true>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, \
+                                             partials, part_off, stream)                              \
+                : launch_batch_t<S, A, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, \
+                                              partials, part_off, stream);
+    switch (prec) {
+    case PREC_C64: GP_SB_PREC(float2, float)
+    case PREC_C64_F64: GP_SB_PREC(float2, double)
+    case PREC_C128: GP_SB_PREC(double2, double)
+    }
+#undef GP_SB_PREC
+    return hipErrorInvalidValue;
 }
 
 template <typename S, typename A, bool REAL>

@@ -1,0 +1,176 @@
+"""Batches (gp_batch_*): many solves advanced together.
+
+A solve inside a batch runs the same per-line arithmetic as a single plan
+(the same device functions, launch shapes that do not enter the rounding,
+norm partials per line), so its result must be bitwise the single plan's --
+alone or in any mix, with or without graph replay and autotuning.  The
+single plans are themselves checked against the oracle in
+test_gpu_parity.py; a few cases here go straight to the oracle too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1206_1361_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1206_1361_amd as gp  # noqa: E402
+
+MODES = {"imag": oracle.IMAG, "real": oracle.REAL}
+
+
+def specs_mixed(seed=0, n=7):
+    """Uneven grids (three shapes, one repeated), per-solve traps and g."""
+    rng = np.random.default_rng(seed)
+    shapes = [(24, 20, 16), (33, 17, 9), (24, 20, 16), (48, 40, 32), (33, 17, 9), (24, 20, 16), (48, 40, 32)]
+    out = []
+    for i in range(n):
+        trap = tuple(rng.uniform(0.5, 3.0, 3))
+        out.append(dict(grid=shapes[i % len(shapes)], dx=0.3, dt=0.01, trap=trap,
+                        g=float(np.exp(rng.uniform(0, np.log(1000.0))))))
+    return out
+
+
+def initial(sp, seed, dtype):
+    psi = inputs.smooth_random_state(sp["grid"], (sp["dx"],) * 3, sp["trap"], seed=seed)
+    t = torch.from_numpy(psi)
+    return t.to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+
+
+def run_single(sp, psi0, mode, dtype, nsteps, calls=1):
+    psi = psi0.clone()
+    with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode=mode, dtype=dtype) as p:
+        for c in range(calls):
+            p.step(psi, nsteps)
+        obs = p.observables(psi)
+    return psi, obs
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["imag", "real"])
+def test_batch_matches_single_plans_bitwise(mode, dtype, graph):
+    specs = specs_mixed(1)
+    psi0 = [initial(sp, 10 + i, dtype) for i, sp in enumerate(specs)]
+    psis = [t.clone() for t in psi0]
+    with gp.Batch(specs, mode=mode, dtype=dtype, graph=graph) as b:
+        b.bind(psis)
+        b.step(4)
+        b.step(3)
+        obs = b.observables()
+    for i, sp in enumerate(specs):
+        ref = psi0[i].clone()
+        with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode=mode, dtype=dtype) as p:
+            p.step(ref, 4)
+            p.step(ref, 3)
+            robs = p.observables(ref)
+        assert torch.equal(psis[i], ref), i
+        for k in ("mu", "energy", "norm", "rms_r"):
+            assert obs[i][k] == robs[k], (i, k)
+
+
+def test_batch_matches_oracle():
+    specs = specs_mixed(2, n=4)
+    psi0 = [initial(sp, 20 + i, "c128") for i, sp in enumerate(specs)]
+    psis = [t.clone() for t in psi0]
+    with gp.Batch(specs, mode="imag", dtype="c128") as b:
+        b.bind(psis)
+        b.step(5)
+        obs = b.observables()
+    for i, sp in enumerate(specs):
+        ref = psi0[i].cpu().numpy().copy()
+        oracle.step(ref, (sp["dx"],) * 3, sp["dt"], sp["trap"], sp["g"], oracle.IMAG, 5)
+        got = psis[i].cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        robs = oracle.observables(ref, (sp["dx"],) * 3, sp["trap"], sp["g"])
+        assert abs(obs[i]["mu"] - robs["mu"]) <= 1e-12 * abs(robs["mu"])
+
+
+def test_alone_and_in_the_mix_are_bitwise_equal():
+    """A solve gives the same bits in a batch of one and inside a larger,
+    autotuned batch."""
+    specs = specs_mixed(3)
+    target = 3
+    psi0 = [initial(sp, 30 + i, "c64") for i, sp in enumerate(specs)]
+    mix = [t.clone() for t in psi0]
+    with gp.Batch(specs, mode="imag", dtype="c64", tune=True) as b:
+        b.bind(mix)
+        b.step(6)
+    alone = [psi0[target].clone()]
+    with gp.Batch([specs[target]], mode="imag", dtype="c64") as b:
+        b.bind(alone)
+        b.step(6)
+    assert torch.equal(mix[target], alone[0])
+
+
+def test_inactive_solves_are_untouched():
+    specs = specs_mixed(4, n=5)
+    psi0 = [initial(sp, 40 + i, "c128") for i, sp in enumerate(specs)]
+    psis = [t.clone() for t in psi0]
+    mask = [True, False, True, False, True]
+    with gp.Batch(specs, mode="real", dtype="c128") as b:
+        b.bind(psis)
+        b.set_active(mask)
+        b.step(3)
+        obs = b.observables()
+    for i, sp in enumerate(specs):
+        if mask[i]:
+            ref, _ = run_single(sp, psi0[i], "real", "c128", 3)
+            assert torch.equal(psis[i], ref)
+        else:
+            assert torch.equal(psis[i], psi0[i])
+
+
+def test_graph_replays_match_eager_across_calls():
+    """Replays of the captured step, with the program's own eager work and
+    synchronisations between them, equal eager launches every time."""
+    specs = specs_mixed(5)
+    psi0 = [initial(sp, 50 + i, "c128") for i, sp in enumerate(specs)]
+    a = [t.clone() for t in psi0]
+    e = [t.clone() for t in psi0]
+    with gp.Batch(specs, mode="imag", dtype="c128", graph=True) as bg, \
+            gp.Batch(specs, mode="imag", dtype="c128", graph=False) as be:
+        bg.bind(a)
+        be.bind(e)
+        for call in range(4):
+            bg.step(2)
+            be.step(2)
+            scratch = torch.ones(1000, device="cuda").sum()   # unrelated eager work
+            torch.cuda.synchronize()
+            assert float(scratch) == 1000.0
+            for i in range(len(specs)):
+                assert torch.equal(a[i], e[i]), (call, i)
+
+
+def test_solve_imag_stops_each_solve_on_its_own():
+    specs = specs_mixed(6, n=5)
+    for sp in specs:
+        sp["dt"] = 0.02
+    psis = [initial(sp, 60 + i, "c128") for i, sp in enumerate(specs)]
+    with gp.Batch(specs, mode="imag", dtype="c128") as b:
+        b.bind(psis)
+        obs, steps, conv = b.solve_imag(tol=1e-6, check_every=10, max_steps=3000)
+        assert all(conv), (steps, conv)
+        assert len(set(steps)) > 1            # solves stopped at different times
+        again = b.observables()
+    for i, sp in enumerate(specs):
+        # the stopped state is the single plan's state after the same calls
+        assert steps[i] % 10 == 0
+        ref, robs = run_single(sp, initial(sp, 60 + i, "c128"), "imag", "c128", 10, calls=steps[i] // 10)
+        assert torch.equal(psis[i], ref), i
+        assert again[i]["mu"] == robs["mu"]
+        assert abs(obs[i]["mu"] - robs["mu"]) == 0.0
+
+
+def test_batch_binding_checks():
+    specs = specs_mixed(7, n=2)
+    with gp.Batch(specs, mode="imag", dtype="c128") as b:
+        with pytest.raises(gp.GPInvalid):
+            b.step(1)                       # nothing bound yet
+        with pytest.raises(ValueError):
+            b.bind([initial(specs[0], 1, "c128")])
+        with pytest.raises(ValueError):
+            b.bind([initial(specs[0], 1, "c64"), initial(specs[1], 2, "c64")])
+        assert "2 solves" in b.describe()

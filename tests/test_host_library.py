@@ -88,7 +88,7 @@ def test_footprint():
     assert gp.footprint_bytes((0, 8, 8)) == 0
     small = gp.footprint_bytes((32, 32, 32))
     large = gp.footprint_bytes((512, 512, 384))
-    assert 0 < small < large < 1 << 20        # tables + scratch only, not psi
+    assert 0 < small < large < 8 << 20        # tables + scratch only (O(Nx Ny)), not psi
     assert gp.footprint_bytes((512, 512, 384), "c64") < large
 
 
@@ -220,3 +220,33 @@ def test_gpu_path_and_oracle_share_no_code():
         if f.endswith((".py", ".c", ".h")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1206_1361_amd" not in text and "gpssc" not in text, f
+
+
+def test_batch_create_rejects_bad_arguments_before_any_device_call():
+    L = gp.lib()
+    i64 = ctypes.c_int64
+    dbl = ctypes.c_double
+
+    def create(n=2, grids=None, dx=0.2, dt=0.004, trap=1.0, g=1.0, mode=0, dtype=1, flags=0):
+        grids = grids or [8, 8, 8] * n
+        G = (i64 * len(grids))(*grids)
+        D = (dbl * (3 * n))(*([dx] * (3 * n)))
+        T = (dbl * n)(*([dt] * n))
+        W = (dbl * (3 * n))(*([trap] * (3 * n)))
+        Gs = (dbl * n)(*([g] * n))
+        out = ctypes.c_void_p(99)
+        st = L.gp_batch_create(n, G, D, T, W, Gs, mode, dtype, flags, None, ctypes.byref(out))
+        return st, out.value
+
+    assert create(n=0) == (_binding.ERR_INVALID, None)
+    assert create(grids=[8, 8, 8, 0, 8, 8]) == (_binding.ERR_INVALID, None)
+    assert create(dx=-1.0) == (_binding.ERR_INVALID, None)
+    assert create(dt=float("nan")) == (_binding.ERR_INVALID, None)
+    assert create(trap=-0.5) == (_binding.ERR_INVALID, None)
+    assert create(g=float("inf")) == (_binding.ERR_INVALID, None)
+    assert create(mode=5) == (_binding.ERR_INVALID, None)
+    assert create(flags=8) == (_binding.ERR_INVALID, None)
+    assert create(grids=[8, 8, 8, 8, 2000, 8]) == (_binding.ERR_UNSUPPORTED, None)
+    assert L.gp_batch_destroy(None) == _binding.OK
+    assert L.gp_batch_step(None, 1) == _binding.ERR_INVALID
+    assert L.gp_batch_observables(None, None) == _binding.ERR_INVALID
