@@ -16,7 +16,11 @@ events recorded on the plan's stream inside the timed region, against the
 8 TB/s HBM3E peak.  `cpu_baseline` is the FP64 oracle timed on this host's
 cores over a bounded sample of the same workload.  `latency` is the
 end-to-end time of the small imaginary-time solve (32^3, 200 steps),
-upload to observables on the host, p50/p99 over repeated solves.
+upload to observables on the host, p50/p99 over repeated solves.  `batch`
+runs 256 uneven imaginary-time ground-state solves (grids 48^3 to 160^3,
+dx 0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between
+checks 10 steps apart) as one complex64 batch and, for comparison, one by
+one on complex128 plans, with the complex64 error at equal step counts.
 """
 from __future__ import annotations
 
@@ -153,6 +157,101 @@ def latency(gp, torch, repeats: int) -> dict:
             "p99_ms": round(float(np.percentile(times, 99)), 3)}
 
 
+def _solve_plan(gp, torch, sp, psi, dtype, tol, check_every, max_steps):
+    """One solve on its own plan, stopped by the same |delta mu| rule as
+    gp_batch_solve_imag."""
+    with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode="imag", dtype=dtype) as p:
+        last = p.observables(psi)["mu"]
+        done = 0
+        while done < max_steps:
+            k = min(check_every, max_steps - done)
+            p.step(psi, k)
+            done += k
+            obs = p.observables(psi)
+            if abs(obs["mu"] - last) < tol:
+                return obs, done, True
+            last = obs["mu"]
+    return obs, done, False
+
+
+def batch_bench(gp, torch, nsolves: int, tol: float, check_every: int, max_steps: int, sample: int) -> dict:
+    """Many uneven imaginary-time solves: the complex64 batch (FP64 reductions,
+    graph replay, tuned launch shapes, per-solve stopping) against the same
+    solves run one by one on complex128 plans with the same stopping rule."""
+    from paper_1206_1361_amd import inputs
+
+    specs = inputs.batch_imag_specs(nsolves)
+    classes = {}
+    for sp in specs:
+        key = "x".join(map(str, sp["grid"]))
+        classes[key] = classes.get(key, 0) + 1
+    start = lambda sp: inputs.gaussian(sp["grid"], (sp["dx"],) * 3, sp["trap"])  # noqa: E731
+    pts = [int(np.prod(sp["grid"])) for sp in specs]
+
+    log(f"[bench] batch: {nsolves} complex64 solves {classes}")
+    psis = [torch.from_numpy(start(sp)).to(torch.complex64).cuda() for sp in specs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with gp.Batch(specs, mode="imag", dtype="c64", graph=True, tune=True) as b:
+        b.bind(psis)
+        obs32, steps32, conv32 = b.solve_imag(tol=tol, check_every=check_every, max_steps=max_steps)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    log(f"[bench] batch: complex64 batch {t32:.2f} s, {sum(conv32)}/{nsolves} converged")
+
+    log("[bench] batch: the same solves one by one on complex128 plans")
+    t64 = 0.0
+    obs64, steps64, conv64 = [], [], []
+    for sp in specs:
+        psi = torch.from_numpy(start(sp)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o, n, c = _solve_plan(gp, torch, sp, psi, "c128", tol, check_every, max_steps)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        obs64.append(o)
+        steps64.append(n)
+        conv64.append(c)
+        del psi
+    log(f"[bench] batch: complex128 one by one {t64:.2f} s, {sum(conv64)}/{nsolves} converged")
+
+    # precision alone: complex128 plans run to the batch's own step counts
+    idx = list(range(0, nsolves, max(1, nsolves // sample)))[:sample]
+    mu_err, psi_err = [], []
+    for i in idx:
+        sp = specs[i]
+        psi = torch.from_numpy(start(sp)).cuda()
+        with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode="imag", dtype="c128") as p:
+            for _ in range(steps32[i] // check_every):
+                p.step(psi, check_every)
+            p.step(psi, steps32[i] % check_every)
+            mu = p.observables(psi)["mu"]
+        mu_err.append(abs(obs32[i]["mu"] - mu) / abs(mu))
+        ref = psi.abs().max().item()
+        psi_err.append((psis[i].to(torch.complex128) - psi).abs().max().item() / ref)
+        del psi
+    stop_err = [abs(obs32[i]["mu"] - obs64[i]["mu"]) / abs(obs64[i]["mu"]) for i in range(nsolves)]
+    return {
+        "workload": f"imag-batch-{nsolves}", "solves": nsolves, "classes": classes,
+        "dx": specs[0]["dx"], "dt": specs[0]["dt"], "stop": f"|dmu| < {tol:g} between checks {check_every} steps apart",
+        "max_steps": max_steps,
+        "fp32_batched": {"storage": "complex64", "arithmetic": "f32", "reductions": "f64",
+                         "seconds": round(t32, 3), "solves_per_s": round(nsolves / t32, 2),
+                         "converged": int(sum(conv32)), "steps_total": int(sum(steps32)),
+                         "pt_steps_per_s": sum(p * s for p, s in zip(pts, steps32)) / t32},
+        "fp64_per_solve": {"storage": "complex128", "arithmetic": "f64", "reductions": "f64",
+                           "seconds": round(t64, 3), "solves_per_s": round(nsolves / t64, 2),
+                           "converged": int(sum(conv64)), "steps_total": int(sum(steps64)),
+                           "pt_steps_per_s": sum(p * s for p, s in zip(pts, steps64)) / t64},
+        "speedup": round(t64 / t32, 3),
+        "accuracy": {"sample": f"{len(idx)} solves, complex128 plans run to the batch's step counts",
+                     "mu_rel_max": max(mu_err), "mu_rel_median": float(np.median(mu_err)),
+                     "psi_rel_max": max(psi_err),
+                     "mu_rel_max_vs_fp64_own_stop": max(stop_err),
+                     "mu_rel_median_vs_fp64_own_stop": float(np.median(stop_err))},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +264,10 @@ def main() -> int:
     ap.add_argument("--latency-repeats", type=int, default=50)
     ap.add_argument("--only", choices=["c128", "c64", "c64_f64"], default=None,
                     help="run one dtype only (profiling runs)")
+    ap.add_argument("--batch-solves", type=int, default=256,
+                    help="solves in the batched imaginary-time comparison (0 skips it)")
+    ap.add_argument("--batch-sample", type=int, default=32,
+                    help="solves re-run in complex128 to the batch's step counts for the error figures")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB buffer three times with torch (a plain copy kernel "
                          "of known size, to scale hardware byte counters)")
@@ -230,6 +333,8 @@ def main() -> int:
     if args.latency_repeats > 0:
         log("[bench] latency of the small imaginary-time solve")
         out["latency"] = latency(gp, torch, args.latency_repeats)
+    if args.batch_solves > 0:
+        out["batch"] = batch_bench(gp, torch, args.batch_solves, 1e-8, 10, 20000, args.batch_sample)
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(w, psi_host, args.cpu_seconds)

@@ -158,6 +158,24 @@ LARGE_REAL = Workload(
 
 WORKLOADS = {w.name: w for w in (SMALL_IMAG, QUENCH, LARGE_REAL)}
 
+# Batch of independent imaginary-time ground-state solves of uneven sizes:
+# grids drawn from five shapes, traps uniform in [0.5, 3] per axis, g
+# log-uniform in [1, 1000], dx 0.2, dt = 0.1 dx^2, Gaussian start per solve.
+BATCH_GRIDS = ((48, 48, 48), (64, 64, 64), (96, 64, 48), (128, 96, 64), (160, 160, 160))
+
+
+def batch_imag_specs(n: int = 256, seed: int = 3, dx: float = 0.2, grids=BATCH_GRIDS) -> list:
+    """Seeded specs of a batch of imaginary-time solves (dicts with grid,
+    dx, dt, trap, g)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        grid = tuple(grids[int(rng.integers(len(grids)))])
+        trap = tuple(float(v) for v in rng.uniform(0.5, 3.0, 3))
+        g = float(np.exp(rng.uniform(0.0, np.log(1000.0))))
+        out.append({"grid": grid, "dx": dx, "dt": 0.1 * dx * dx, "trap": trap, "g": g})
+    return out
+
 
 def initial_state(w: Workload, seed: int | None = None) -> np.ndarray:
     """The documented starting state of a workload (host, complex128).
