@@ -253,6 +253,95 @@ gp_status gp_batch_solve_imag(gp_batch *batch, double tol, int64_t check_every, 
 /* One-line description of the classes and launch shapes. */
 gp_status gp_batch_describe(const gp_batch *batch, char *buf, size_t len);
 
+/* ---- Serving: continuous batching of solve requests ------------------
+ *
+ * A server owns one device arena of hbm_budget bytes and an engine thread.
+ * Requests (ground states in imaginary time, dynamics in real time; any
+ * grid, spacing, step, trap and g) are queued by gp_server_submit and
+ * admitted, in arrival order with later requests allowed to pass one that
+ * does not fit yet, whenever a slot and gp_server_request_bytes of the arena
+ * are free; the request's psi, tables and reduction scratch then stay
+ * resident until it finishes.  All resident solves advance together: every
+ * check_every steps the engine admits new requests, and between those points
+ * the solves of one grid shape and mode share one launch per sweep (the
+ * kernels of gp_batch).  A solve's events (the chemical-potential check of an
+ * imaginary-time solve, the end of a run) fall on multiples of check_every
+ * of its own steps, so its result is bitwise the same alone and in any mix,
+ * and equal to a gp_plan stepped check_every steps per gp_step call.
+ * The stopping rule of an imaginary-time request is gp_batch_solve_imag's:
+ * stop when mu moved by less than tol since the previous check, or after
+ * `steps` steps. */
+typedef struct gp_server gp_server;
+
+enum {
+    GP_SERVER_GRAPH = 1  /* capture one step of the resident set in a HIP graph, re-captured when it changes */
+};
+
+typedef struct {
+    int64_t grid[3];      /* Nx, Ny, Nz, each 1..1024 */
+    double dx[3];         /* > 0 */
+    double dt;            /* > 0 */
+    double trap[3];       /* gamma, nu, lambda >= 0 */
+    double g;             /* finite */
+    gp_mode mode;
+    int64_t steps;        /* real time: steps to run; imaginary time: the step cap; >= 1 */
+    double tol;           /* imaginary time: |delta mu| stopping tolerance (0: run to the cap) */
+    const void *psi_in;   /* host memory: the initial state, Nx*Ny*Nz elements of the server's dtype,
+                             in gp_step's layout; read at admission */
+    void *psi_out;        /* host memory for the final state (may be psi_in); written before the
+                             result is reported */
+    uint64_t tag;         /* the caller's, returned in the result */
+} gp_request;
+
+typedef struct {
+    uint64_t id, tag;
+    gp_status status;     /* GP_OK, GP_ERR_NONFINITE (zero or non-finite norm), GP_ERR_DEVICE */
+    int converged;        /* imaginary time: stopped by tol */
+    int64_t steps;        /* steps taken */
+    gp_obs obs;           /* of the final state (steps_done = steps) */
+    double t_submit, t_admit, t_done;  /* seconds on the server's monotonic clock */
+} gp_result;
+
+typedef struct {
+    int64_t submitted, completed, queued, resident, max_resident;
+    int64_t quanta;          /* engine rounds (each check_every steps or fewer) */
+    int64_t graph_captures;
+    int64_t solve_steps;     /* steps summed over solves */
+    uint64_t bytes_in_use, bytes_peak, bytes_budget;
+} gp_server_counters;
+
+/* Device bytes one request of this grid, dtype and mode holds while resident
+ * (psi, its correction tables, reduction scratch), or 0 if the grid is not
+ * supported. */
+size_t gp_server_request_bytes(const int64_t grid[3], gp_dtype dtype, gp_mode mode);
+
+/* Creates a server on the current device: an arena of hbm_budget bytes,
+ * at most max_slots resident requests (1..4096), checks every check_every
+ * steps (>= 1).  GP_ERR_NOMEM if the arena cannot be allocated. */
+gp_status gp_server_create(gp_dtype dtype, uint64_t hbm_budget, int max_slots, int64_t check_every,
+                           int flags, gp_server **out);
+
+/* Stops the engine and frees the server.  Requests not yet reported are
+ * dropped (their host buffers are no longer touched once this returns).
+ * NULL-safe. */
+gp_status gp_server_destroy(gp_server *server);
+
+/* Queues a request; *id identifies its result.  The host buffers must stay
+ * valid until the result is reported.  GP_ERR_INVALID for bad parameters,
+ * GP_ERR_UNSUPPORTED for an unsupported grid, GP_ERR_NOMEM if the request
+ * could never fit the arena, GP_ERR_DEVICE once the engine has failed. */
+gp_status gp_server_submit(gp_server *server, const gp_request *req, uint64_t *id);
+
+/* Moves up to max finished results into out (*n of them), waiting up to
+ * wait_seconds for the first one (0: do not wait). */
+gp_status gp_server_poll(gp_server *server, gp_result *out, int max, double wait_seconds, int *n);
+
+/* Waits up to wait_seconds until no request is queued or resident; *idle
+ * says whether that point was reached.  Results stay until polled. */
+gp_status gp_server_drain(gp_server *server, double wait_seconds, int *idle);
+
+gp_status gp_server_stats(gp_server *server, gp_server_counters *out);
+
 /* Host-only view of the constant coefficients the sweep kernels use along
  * one axis (no device call), for inspection and tests.  For a line of n
  * points, spacing dx, step dt, mode and a chunking with chunk * lanes >= n,

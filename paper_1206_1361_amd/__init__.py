@@ -9,6 +9,6 @@ generators in ``inputs``) needs no GPU.
 """
 from ._binding import (  # noqa: F401
     C64, C64_F64, C128, IMAG, REAL, EXPORTS, KERNELS, Batch, GPError, GPInvalid, GPNoMemory, GPNonFinite,
-    Plan,
-    footprint_bytes, lib, library_path, sweep_shape, sweep_tables,
+    Plan, Server,
+    footprint_bytes, lib, library_path, request_bytes, sweep_shape, sweep_tables,
 )

@@ -36,10 +36,13 @@ EXPORTS = (
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
     "gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active", "gp_batch_step",
     "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe",
+    "gp_server_request_bytes", "gp_server_create", "gp_server_destroy", "gp_server_submit", "gp_server_poll",
+    "gp_server_drain", "gp_server_stats",
 )
 
 BATCH_GRAPH = 1
 BATCH_TUNE = 2
+SERVER_GRAPH = 1
 
 
 class GPError(RuntimeError):
@@ -78,6 +81,29 @@ class GPObs(ctypes.Structure):
             "kinetic": self.kinetic, "potential": self.potential,
             "interaction": self.interaction, "steps_done": self.steps_done,
         }
+
+
+class GPRequest(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3), ("dt", ctypes.c_double),
+        ("trap", ctypes.c_double * 3), ("g", ctypes.c_double), ("mode", ctypes.c_int),
+        ("steps", ctypes.c_int64), ("tol", ctypes.c_double), ("psi_in", ctypes.c_void_p),
+        ("psi_out", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+    ]
+
+
+class GPResult(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("converged", ctypes.c_int),
+        ("steps", ctypes.c_int64), ("obs", GPObs), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class GPServerCounters(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "queued", "resident", "max_resident",
+                                                "quanta", "graph_captures", "solve_steps")] + \
+               [(n, ctypes.c_uint64) for n in ("bytes_in_use", "bytes_peak", "bytes_budget")]
 
 
 _lib = None
@@ -133,6 +159,18 @@ def lib() -> ctypes.CDLL:
     L.gp_batch_observables.argtypes = [vp, ctypes.POINTER(GPObs)]
     L.gp_batch_solve_imag.argtypes = [vp, dbl, i64, i64, ctypes.POINTER(GPObs), i64p, up]
     L.gp_batch_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.gp_server_request_bytes.argtypes = [i64p, ctypes.c_int, ctypes.c_int]
+    L.gp_server_request_bytes.restype = sz
+    L.gp_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, i64, ctypes.c_int,
+                                   ctypes.POINTER(vp)]
+    L.gp_server_destroy.argtypes = [vp]
+    L.gp_server_submit.argtypes = [vp, ctypes.POINTER(GPRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.gp_server_poll.argtypes = [vp, ctypes.POINTER(GPResult), ctypes.c_int, dbl, ip]
+    L.gp_server_drain.argtypes = [vp, dbl, ip]
+    L.gp_server_stats.argtypes = [vp, ctypes.POINTER(GPServerCounters)]
+    for name in ("gp_server_create", "gp_server_destroy", "gp_server_submit", "gp_server_poll",
+                 "gp_server_drain", "gp_server_stats"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active",
                  "gp_batch_step", "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe"):
         getattr(L, name).restype = ctypes.c_int
@@ -163,14 +201,20 @@ def _mode(mode) -> int:
 
 
 def _dtype(dtype) -> int:
+    if isinstance(dtype, (int, str)):
+        if dtype in (C128, "c128", "complex128"):
+            return C128
+        if dtype in (C64, "c64", "complex64"):
+            return C64
+        if dtype in (C64_F64, "c64_f64"):
+            return C64_F64
+        raise ValueError(f"unknown dtype {dtype!r}")
     import torch
 
-    if dtype in (C128, "c128", "complex128", torch.complex128):
+    if dtype == torch.complex128:
         return C128
-    if dtype in (C64, "c64", "complex64", torch.complex64):
+    if dtype == torch.complex64:
         return C64
-    if dtype in (C64_F64, "c64_f64"):
-        return C64_F64
     raise ValueError(f"unknown dtype {dtype!r}")
 
 
@@ -421,6 +465,126 @@ class Batch:
         if getattr(self, "_handle", None) and self._handle.value:
             lib().gp_batch_destroy(self._handle)
             self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def request_bytes(grid, dtype="c64", mode="imag") -> int:
+    """Device bytes a served request of this grid holds while resident (0:
+    unsupported grid)."""
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    return int(lib().gp_server_request_bytes(g, _dtype(dtype), _mode(mode)))
+
+
+_servers = None
+
+
+def _close_servers():
+    for srv in list(_servers or ()):
+        srv.close()
+
+
+class Server:
+    """Continuous-batching request server (gp_server_*).
+
+    Requests carry host (numpy) states of the server's dtype, shaped
+    (Nz, Ny, Nx); the engine thread in the library admits them by device
+    footprint, advances all resident solves together and writes each final
+    state to the request's output array before reporting it.
+    """
+
+    def __init__(self, dtype="c64", hbm_budget: int = 8 << 30, max_slots: int = 64, check_every: int = 10,
+                 graph: bool = True):
+        import atexit
+        import weakref
+
+        import numpy as np
+
+        global _servers
+        L = lib()
+        self.dtype = _dtype(dtype)
+        self.np_dtype = np.complex128 if self.dtype == C128 else np.complex64
+        self.check_every = int(check_every)
+        self._handle = ctypes.c_void_p()
+        self._held = {}
+        _check(L.gp_server_create(self.dtype, int(hbm_budget), int(max_slots), self.check_every,
+                                  SERVER_GRAPH if graph else 0, ctypes.byref(self._handle)), "gp_server_create")
+        if _servers is None:
+            _servers = weakref.WeakSet()
+            atexit.register(_close_servers)
+        _servers.add(self)
+
+    def submit(self, psi_in, *, dx, dt, trap, g, mode="imag", steps, tol=0.0, psi_out=None, tag=0) -> int:
+        """Queue one request; returns its id.  psi_in (and psi_out, default a
+        new array) are kept referenced until the result is polled."""
+        import numpy as np
+
+        if not isinstance(psi_in, np.ndarray) or psi_in.dtype != self.np_dtype or psi_in.ndim != 3 \
+                or not psi_in.flags.c_contiguous:
+            raise ValueError(f"psi_in must be a C-contiguous {np.dtype(self.np_dtype).name} array (Nz, Ny, Nx)")
+        if psi_out is None:
+            psi_out = np.empty_like(psi_in)
+        elif psi_out.shape != psi_in.shape or psi_out.dtype != psi_in.dtype or not psi_out.flags.c_contiguous \
+                or not psi_out.flags.writeable:
+            raise ValueError("psi_out must be a writeable C-contiguous array like psi_in")
+        nz, ny, nx = psi_in.shape
+        dxs = tuple(float(v) for v in (dx if hasattr(dx, "__len__") else (dx,) * 3))
+        r = GPRequest()
+        r.grid[:] = [nx, ny, nz]
+        r.dx[:] = dxs
+        r.dt = float(dt)
+        r.trap[:] = [float(v) for v in trap]
+        r.g = float(g)
+        r.mode = _mode(mode)
+        r.steps = int(steps)
+        r.tol = float(tol)
+        r.psi_in = psi_in.ctypes.data
+        r.psi_out = psi_out.ctypes.data
+        r.tag = int(tag)
+        rid = ctypes.c_uint64()
+        _check(lib().gp_server_submit(self._handle, ctypes.byref(r), ctypes.byref(rid)), "gp_server_submit")
+        self._held[rid.value] = (psi_in, psi_out)
+        return rid.value
+
+    def poll(self, max_results: int = 256, wait: float = 0.0) -> list:
+        """Finished results (dicts), waiting up to `wait` seconds for the first."""
+        out = (GPResult * max_results)()
+        n = ctypes.c_int()
+        _check(lib().gp_server_poll(self._handle, out, max_results, float(wait), ctypes.byref(n)), "gp_server_poll")
+        res = []
+        for r in out[:n.value]:
+            held = self._held.pop(r.id, (None, None))
+            res.append({"id": r.id, "tag": r.tag, "status": r.status, "converged": bool(r.converged),
+                        "steps": r.steps, "obs": r.obs.as_dict(), "t_submit": r.t_submit, "t_admit": r.t_admit,
+                        "t_done": r.t_done, "psi": held[1]})
+        return res
+
+    def drain(self, wait: float = 600.0) -> bool:
+        """Wait until nothing is queued or resident; True if reached."""
+        idle = ctypes.c_int()
+        _check(lib().gp_server_drain(self._handle, float(wait), ctypes.byref(idle)), "gp_server_drain")
+        return bool(idle.value)
+
+    def stats(self) -> dict:
+        c = GPServerCounters()
+        _check(lib().gp_server_stats(self._handle, ctypes.byref(c)), "gp_server_stats")
+        return {name: getattr(c, name) for name, _ in GPServerCounters._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) and self._handle.value:
+            lib().gp_server_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -23,27 +23,21 @@
 #include "gp_internal.h"
 #include "gpssc.h"
 #include "host_common.h"
+#include "solve_host.h"
 
 using namespace gpssc_host;
 
 namespace {
 
-struct Solve {
-    int64_t grid[3];
-    double dx[3], dt, omega[3], g;
-    AxisTables ax[3];
+struct Solve : SolveDesc {
     int cls;
-    int64_t elems;
     int64_t part_off;        // into the per-line norm partials
-    int64_t zt_off[3];       // bytes into the correction tables
+    int64_t obs_off;         // into the observables partials
+    size_t tab_off;          // bytes into the correction tables
     void *psi = nullptr;
 };
 
-struct Class {
-    int64_t grid[3];
-    int chunk[3], lanes[3];
-    int xt_y, xt_z;
-    int nlines, ncol_y, ntiles_y, ncol_z, ntiles_z, obs_blocks;
+struct Class : ClassShape {
     std::vector<int> members;
     int nact = 0;
     int *d_active = nullptr;     // active solve indices
@@ -69,6 +63,7 @@ struct gp_batch {
     void **d_psis = nullptr;
     double *d_partials = nullptr;
     int64_t *d_part_off = nullptr;
+    int64_t *d_obs_off = nullptr;
     double *d_dv = nullptr;
     double *d_scales = nullptr;
     int *d_flags = nullptr;
@@ -98,56 +93,22 @@ bool bound(const gp_batch *b)
 void release(gp_batch *b)
 {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (Class &c : b->cls)
-        if (c.d_active) hipFree(c.d_active);
+        if (c.d_active) (void)hipFree(c.d_active);
     void *dev[] = {b->d_tables, b->d_xargs, b->d_yargs, b->d_zargs, b->d_psis, b->d_partials,
-                   b->d_part_off, b->d_dv, b->d_scales, b->d_flags, b->d_obsargs,
+                   b->d_part_off, b->d_obs_off, b->d_dv, b->d_scales, b->d_flags, b->d_obsargs,
                    b->d_obs_partials, b->d_sums};
     for (void *p : dev)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     void *host[] = {b->h_sums, b->h_flags, b->h_psis, b->h_active};
     for (void *p : host)
-        if (p) hipHostFree(p);
-    if (b->ev_in) hipEventDestroy(b->ev_in);
-    if (b->ev_out) hipEventDestroy(b->ev_out);
-    if (b->own) hipStreamDestroy(b->own);
+        if (p) (void)hipHostFree(p);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
-}
-
-template <typename A>
-void fill_solve_args(const Solve &x, const unsigned char *d_tables, gpssc::XBatchArgs<A> &xa,
-                     gpssc::SBatchArgs<A> &ya, gpssc::SBatchArgs<A> &za, const Class &c)
-{
-    gpssc::XArgs<A> &a = xa.x;
-    a.nx = (int)x.grid[0];
-    a.ny = (int)x.grid[1];
-    a.nz = (int)x.grid[2];
-    a.c0x = (A)(0.5 * (double)(x.grid[0] - 1));
-    a.c0y = (A)(0.5 * (double)(x.grid[1] - 1));
-    a.c0z = (A)(0.5 * (double)(x.grid[2] - 1));
-    a.dx = (A)x.dx[0];
-    a.dy = (A)x.dx[1];
-    a.dz = (A)x.dx[2];
-    a.hgx = (A)(0.5 * x.omega[0] * x.omega[0]);
-    a.hgy = (A)(0.5 * x.omega[1] * x.omega[1]);
-    a.hgz = (A)(0.5 * x.omega[2] * x.omega[2]);
-    a.dt = (A)x.dt;
-    a.g = (A)x.g;
-    a.k = sweep_coef<A>(x.ax[0], x.dt, x.dx[0]);
-    xa.zt = reinterpret_cast<const cx<A> *>(d_tables + x.zt_off[0]);
-    gpssc::SBatchArgs<A> *yz[2] = {&ya, &za};
-    for (int ax = 1; ax < 3; ++ax) {
-        gpssc::SArgs<A> &t = yz[ax - 1]->s;
-        t.nx = (int)x.grid[0];
-        t.n = (int)x.grid[ax];
-        t.lanes = c.lanes[ax];
-        t.stride = ax == 1 ? x.grid[0] : x.grid[0] * x.grid[1];
-        t.outer_stride = ax == 1 ? x.grid[0] * x.grid[1] : x.grid[0];
-        t.k = sweep_coef<A>(x.ax[ax], x.dt, x.dx[ax]);
-        yz[ax - 1]->zt = reinterpret_cast<const cx<A> *>(d_tables + x.zt_off[ax]);
-    }
 }
 
 template <typename A>
@@ -157,7 +118,7 @@ std::vector<unsigned char> pack_batch_args(const gp_batch *b, int which)
     for (const Solve &x : b->s) {
         gpssc::XBatchArgs<A> xa;
         gpssc::SBatchArgs<A> ya, za;
-        fill_solve_args<A>(x, b->d_tables, xa, ya, za, b->cls[(size_t)x.cls]);
+        fill_solve_args<A>(x, b->cls[(size_t)x.cls], b->d_tables + x.tab_off, xa, ya, za);
         const unsigned char *p;
         size_t len;
         if (which == 0) {
@@ -229,8 +190,8 @@ hipError_t enqueue_step(gp_batch *b)
 
 hipError_t build_graph(gp_batch *b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_ok = false;
@@ -311,23 +272,13 @@ hipError_t tune_class(gp_batch *b, Class &c)
         else
             c.xt_z = best;
     }
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
-    if (d_m0) hipFree(d_m0);
-    if (d_ptr) hipFree(d_ptr);
-    if (d_one) hipFree(d_one);
-    hipFree(scratch);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (d_m0) (void)hipFree(d_m0);
+    if (d_ptr) (void)hipFree(d_ptr);
+    if (d_one) (void)hipFree(d_one);
+    (void)hipFree(scratch);
     return e;
-}
-
-void class_shapes(Class &c)
-{
-    c.nlines = (int)(c.grid[1] * c.grid[2]);
-    c.ncol_y = (int)((c.grid[0] + c.xt_y - 1) / c.xt_y);
-    c.ntiles_y = c.ncol_y * (int)c.grid[2];
-    c.ncol_z = (int)((c.grid[0] + c.xt_z - 1) / c.xt_z);
-    c.ntiles_z = c.ncol_z * (int)c.grid[1];
-    c.obs_blocks = gpssc::obs_num_blocks((int)c.grid[0], (int)c.grid[1]);
 }
 
 hipError_t sync_in(gp_batch *b)
@@ -342,34 +293,6 @@ hipError_t sync_out(gp_batch *b)
     hipError_t e = hipEventRecord(b->ev_out, b->own);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->caller, b->ev_out, 0);
     return e;
-}
-
-gp_status obs_from_sums(const double *S, const Solve &x, gp_obs *out, int64_t steps)
-{
-    const double dv = x.dx[0] * x.dx[1] * x.dx[2];
-    const double norm = dv * S[gpssc::OBS_DENS];
-    const double kin = 0.5 * dv *
-                       (S[gpssc::OBS_LINKX] / (x.dx[0] * x.dx[0]) + S[gpssc::OBS_LINKY] / (x.dx[1] * x.dx[1]) +
-                        S[gpssc::OBS_LINKZ] / (x.dx[2] * x.dx[2]));
-    const double pot = dv * S[gpssc::OBS_POT];
-    const double inter = x.g * dv * S[gpssc::OBS_QUART];
-    out->norm = norm;
-    out->kinetic = kin / norm;
-    out->potential = pot / norm;
-    out->interaction = inter / (norm * norm);
-    out->energy = out->kinetic + out->potential + 0.5 * out->interaction;
-    out->mu = out->kinetic + out->potential + out->interaction;
-    double r2 = 0.0;
-    for (int q = 0; q < 3; ++q) {
-        const double m2 = dv * S[gpssc::OBS_M2X + q] / norm;
-        out->rms[q] = std::sqrt(m2);
-        out->mean[q] = dv * S[gpssc::OBS_M1X + q] / norm;
-        r2 += m2;
-    }
-    out->rms_r = std::sqrt(r2);
-    out->steps_done = steps;
-    bool ok = norm > 0.0 && std::isfinite(out->mu) && std::isfinite(out->energy) && std::isfinite(out->rms_r);
-    return ok ? GP_OK : GP_ERR_NONFINITE;
 }
 
 }  // namespace
@@ -389,17 +312,9 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE)) return fail(GP_ERR_INVALID, "unknown flags");
     for (int i = 0; i < nsolves; ++i) {
         if (!valid_grid(grids + 3 * i)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
-        for (int a = 0; a < 3; ++a) {
-            if (!finite_pos(dx[3 * i + a])) return fail(GP_ERR_INVALID, "dx must be finite and > 0");
-            if (!std::isfinite(traps[3 * i + a]) || traps[3 * i + a] < 0.0)
-                return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
-        }
-        if (!finite_pos(dt[i])) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
-        if (!std::isfinite(g[i])) return fail(GP_ERR_INVALID, "g must be finite");
-        int c, l;
-        for (int a = 0; a < 3; ++a)
-            if (!sweep_shape(grids[3 * i + a], a, &c, &l, max_lanes_for(dtype)))
-                return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
+        if (!valid_params(dx + 3 * i, dt[i], traps + 3 * i, g[i]))
+            return fail(GP_ERR_INVALID, "dx and dt must be finite and > 0, traps finite and >= 0, g finite");
+        if (!grid_supported(grids + 3 * i, dtype)) return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
     }
     gp_batch *b = new (std::nothrow) gp_batch();
     if (!b) return fail(GP_ERR_NOMEM, "host allocation failed");
@@ -420,9 +335,8 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     // classes by grid shape
     std::map<std::tuple<int64_t, int64_t, int64_t>, int> index;
     b->s.resize((size_t)nsolves);
-    int64_t part = 0;
+    int64_t part = 0, obs = 0;
     size_t tab_bytes = 0;
-    const size_t cs = dtype == GP_C64 ? sizeof(cx<float>) : sizeof(cx<double>);
     for (int i = 0; i < nsolves; ++i) {
         Solve &x = b->s[(size_t)i];
         for (int a = 0; a < 3; ++a) {
@@ -432,51 +346,30 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         }
         x.dt = dt[i];
         x.g = g[i];
-        x.elems = x.grid[0] * x.grid[1] * x.grid[2];
+        x.real = real;
         auto key = std::make_tuple(x.grid[0], x.grid[1], x.grid[2]);
         auto it = index.find(key);
         if (it == index.end()) {
             Class c;
-            for (int a = 0; a < 3; ++a) {
-                c.grid[a] = x.grid[a];
-                sweep_shape(x.grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype));
-            }
-            c.xt_y = strided_columns(c.grid[0], c.lanes[1]);
-            c.xt_z = strided_columns(c.grid[0], c.lanes[2]);
-            class_shapes(c);
+            static_cast<ClassShape &>(c) = class_shape(x.grid, dtype);
             it = index.emplace(key, (int)b->cls.size()).first;
             b->cls.push_back(c);
         }
         x.cls = it->second;
         Class &c = b->cls[(size_t)x.cls];
         c.members.push_back(i);
-        for (int a = 0; a < 3; ++a) {
-            build_axis(x.grid[a], x.dx[a], x.dt, real, c.chunk[a], c.lanes[a], x.ax[a]);
-            x.zt_off[a] = (int64_t)tab_bytes;
-            tab_bytes += cs * (size_t)c.chunk[a] * (size_t)c.lanes[a];
-        }
+        build_solve(x, c);
+        x.tab_off = tab_bytes;
+        tab_bytes += table_bytes(c, dtype);
         x.part_off = part;
         part += x.grid[0] * x.grid[1];
+        x.obs_off = obs;
+        obs += (int64_t)c.obs_blocks * gpssc::OBS_NSUMS;
     }
     b->active.assign((size_t)nsolves, 1);
     // tables
     std::vector<unsigned char> tab(tab_bytes, 0);
-    for (const Solve &x : b->s) {
-        const size_t off3[3] = {(size_t)x.zt_off[0], (size_t)x.zt_off[1], (size_t)x.zt_off[2]};
-        for (int a = 0; a < 3; ++a) {
-            for (int64_t q = 0; q < x.grid[a]; ++q) {
-                if (dtype == GP_C64) {
-                    const cx<float> v = to_cx<float>(x.ax[a].zt[(size_t)q]);
-                    std::memcpy(&tab[off3[a] + (size_t)q * sizeof v], &v, sizeof v);
-                } else {
-                    const cx<double> v = to_cx<double>(x.ax[a].zt[(size_t)q]);
-                    std::memcpy(&tab[off3[a] + (size_t)q * sizeof v], &v, sizeof v);
-                }
-            }
-        }
-    }
-    int max_obs = 0;
-    for (const Class &c : b->cls) max_obs = std::max(max_obs, c.obs_blocks);
+    for (const Solve &x : b->s) pack_solve_tables(x, b->cls[(size_t)x.cls], dtype, tab.data() + x.tab_off);
 #define GB_ALLOC(ptr, bytes)                                                          \
     do {                                                                              \
         e = hipMalloc((void **)&(ptr), (bytes));                                      \
@@ -496,11 +389,12 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     GB_ALLOC(b->d_psis, sizeof(void *) * (size_t)nsolves);
     GB_ALLOC(b->d_partials, sizeof(double) * (size_t)std::max<int64_t>(part, 1));
     GB_ALLOC(b->d_part_off, sizeof(int64_t) * (size_t)nsolves);
+    GB_ALLOC(b->d_obs_off, sizeof(int64_t) * (size_t)nsolves);
     GB_ALLOC(b->d_dv, sizeof(double) * (size_t)nsolves);
     GB_ALLOC(b->d_scales, sizeof(double) * (size_t)nsolves);
     GB_ALLOC(b->d_flags, sizeof(int) * (size_t)nsolves);
     GB_ALLOC(b->d_obsargs, sizeof(gpssc::ObsArgs<double>) * (size_t)nsolves);
-    GB_ALLOC(b->d_obs_partials, sizeof(double) * gpssc::OBS_NSUMS * (size_t)max_obs * (size_t)nsolves);
+    GB_ALLOC(b->d_obs_partials, sizeof(double) * (size_t)obs);
     GB_ALLOC(b->d_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)nsolves);
     for (Class &c : b->cls) GB_ALLOC(c.d_active, sizeof(int) * c.members.size());
 #undef GB_ALLOC
@@ -513,27 +407,16 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         return fail_hip(e, "hipHostMalloc");
     }
     // per-solve constants
-    std::vector<int64_t> offs((size_t)nsolves);
+    std::vector<int64_t> offs((size_t)nsolves), ooffs((size_t)nsolves);
     std::vector<double> dvs((size_t)nsolves), ones((size_t)nsolves, 1.0);
     std::vector<int> zeros((size_t)nsolves, 0);
     std::vector<gpssc::ObsArgs<double>> oa((size_t)nsolves);
     for (int i = 0; i < nsolves; ++i) {
         const Solve &x = b->s[(size_t)i];
         offs[(size_t)i] = x.part_off;
+        ooffs[(size_t)i] = x.obs_off;
         dvs[(size_t)i] = x.dx[0] * x.dx[1] * x.dx[2];
-        gpssc::ObsArgs<double> &o = oa[(size_t)i];
-        o.nx = (int)x.grid[0];
-        o.ny = (int)x.grid[1];
-        o.nz = (int)x.grid[2];
-        o.c0x = 0.5 * (double)(x.grid[0] - 1);
-        o.c0y = 0.5 * (double)(x.grid[1] - 1);
-        o.c0z = 0.5 * (double)(x.grid[2] - 1);
-        o.dx = x.dx[0];
-        o.dy = x.dx[1];
-        o.dz = x.dx[2];
-        o.hgx = 0.5 * x.omega[0] * x.omega[0];
-        o.hgy = 0.5 * x.omega[1] * x.omega[1];
-        o.hgz = 0.5 * x.omega[2] * x.omega[2];
+        oa[(size_t)i] = obs_args(x);
     }
     std::vector<unsigned char> xa = dtype == GP_C64 ? pack_batch_args<float>(b, 0) : pack_batch_args<double>(b, 0);
     std::vector<unsigned char> ya = dtype == GP_C64 ? pack_batch_args<float>(b, 1) : pack_batch_args<double>(b, 1);
@@ -548,6 +431,7 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         {b->d_yargs, ya.data(), ya.size()},
         {b->d_zargs, za.data(), za.size()},
         {b->d_part_off, offs.data(), sizeof(int64_t) * offs.size()},
+        {b->d_obs_off, ooffs.data(), sizeof(int64_t) * ooffs.size()},
         {b->d_dv, dvs.data(), sizeof(double) * dvs.size()},
         {b->d_scales, ones.data(), sizeof(double) * ones.size()},
         {b->d_flags, zeros.data(), sizeof(int) * zeros.size()},
@@ -560,7 +444,7 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         for (Class &c : b->cls) {
             e = dtype == GP_C128 ? tune_class<double2>(b, c) : tune_class<float2>(b, c);
             if (e != hipSuccess) break;
-            class_shapes(c);
+            class_tiles(c);
         }
         // the tuned shapes change the per-solve y/z arguments only through
         // the block shape, which the kernels read from blockDim
@@ -578,7 +462,7 @@ gp_status gp_batch_destroy(gp_batch *b)
 {
     if (!b) return GP_OK;
     DeviceGuard guard(b->device);
-    hipStreamSynchronize(b->own);
+    (void)hipStreamSynchronize(b->own);
     release(b);
     return GP_OK;
 }
@@ -666,7 +550,7 @@ gp_status gp_batch_observables(gp_batch *b, gp_obs *out)
     for (const Class &c : b->cls) {
         if (!c.nact || e != hipSuccess) continue;
         e = gpssc::launch_observables_batch(c64, c.nact, c.d_active, b->d_psis, b->d_obsargs, (int)c.grid[0],
-                                            (int)c.grid[1], b->d_obs_partials, b->d_sums, b->own);
+                                            (int)c.grid[1], b->d_obs_partials, b->d_obs_off, b->d_sums, b->own);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->h_sums, b->d_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)b->n,

@@ -234,9 +234,10 @@ hipError_t launch_norm_finalize_batch(int nact, const int *active, const double 
 hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const *psis,
                               int64_t elems, double *scales, hipStream_t stream);
 
-// Observables sums per solve: sums[i * OBS_NSUMS + q].
+// Observables sums per solve: sums[i * OBS_NSUMS + q].  partials + obs_off[i]:
+// solve i's obs_num_blocks(nx, ny) * OBS_NSUMS doubles of scratch.
 hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
                                     const ObsArgs<double> *args, int nx, int ny, double *partials,
-                                    double *sums, hipStream_t stream);
+                                    const int64_t *obs_off, double *sums, hipStream_t stream);
 
 }  // namespace gpssc

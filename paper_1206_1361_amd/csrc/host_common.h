@@ -202,12 +202,12 @@ class DeviceGuard {
     explicit DeviceGuard(int dev)
     {
         if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-        if (prev_ != dev) hipSetDevice(dev);
+        if (prev_ != dev) (void)hipSetDevice(dev);
         dev_ = dev;
     }
     ~DeviceGuard()
     {
-        if (prev_ >= 0 && prev_ != dev_) hipSetDevice(prev_);
+        if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
     }
 
   private:

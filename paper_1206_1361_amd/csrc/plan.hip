@@ -151,18 +151,18 @@ void release(gp_plan *p)
 {
     if (!p) return;
     for (ProfRec &r : p->prof) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
-    for (hipEvent_t e : p->pool) hipEventDestroy(e);
-    if (p->d_tables) hipFree(p->d_tables);
-    if (p->d_partials) hipFree(p->d_partials);
-    if (p->d_obs_partials) hipFree(p->d_obs_partials);
-    if (p->d_scale) hipFree(p->d_scale);
-    if (p->d_flag) hipFree(p->d_flag);
-    if (p->d_sums) hipFree(p->d_sums);
-    if (p->h_sums) hipHostFree(p->h_sums);
-    if (p->h_flag) hipHostFree(p->h_flag);
+    for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    if (p->d_partials) (void)hipFree(p->d_partials);
+    if (p->d_obs_partials) (void)hipFree(p->d_obs_partials);
+    if (p->d_scale) (void)hipFree(p->d_scale);
+    if (p->d_flag) (void)hipFree(p->d_flag);
+    if (p->d_sums) (void)hipFree(p->d_sums);
+    if (p->h_sums) (void)hipHostFree(p->h_sums);
+    if (p->h_flag) (void)hipHostFree(p->h_flag);
     delete p;
 }
 
@@ -436,7 +436,7 @@ gp_status gp_plan_destroy(gp_plan *plan)
     if (!plan) return GP_OK;
     {
         DeviceGuard guard(plan->device);
-        hipStreamSynchronize(plan->stream);
+        (void)hipStreamSynchronize(plan->stream);
         release(plan);
     }
     return GP_OK;

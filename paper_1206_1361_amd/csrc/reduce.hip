@@ -194,14 +194,13 @@ calcmuen_rms_kernel(const S *__restrict__ psi, const ObsArgs<double> a,
 template <typename S>
 __global__ void __launch_bounds__(kObsX * kObsY)
 calcmuen_rms_batch_kernel(S *const *__restrict__ psis, const int *__restrict__ active,
-                          const ObsArgs<double> *__restrict__ args, double *__restrict__ partials)
+                          const ObsArgs<double> *__restrict__ args, double *__restrict__ partials,
+                          const int64_t *__restrict__ obs_off)
 {
     __shared__ double red[kReduceThreads];
     const int si = active[blockIdx.z];
-    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
     const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    obs_block<S>(psis[si], args[si], partials + ((int64_t)si * nb + b) * OBS_NSUMS, red, blockIdx.x,
-                 blockIdx.y);
+    obs_block<S>(psis[si], args[si], partials + obs_off[si] + b * OBS_NSUMS, red, blockIdx.x, blockIdx.y);
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -220,11 +219,11 @@ obs_finalize_kernel(const double *__restrict__ partials, int nblocks, double *__
 // Batched: block b sums solve active[b]'s partials into sums[si].
 __global__ void __launch_bounds__(kReduceThreads)
 obs_finalize_batch_kernel(const int *__restrict__ active, const double *__restrict__ partials,
-                          int nblocks, double *__restrict__ sums)
+                          const int64_t *__restrict__ obs_off, int nblocks, double *__restrict__ sums)
 {
     __shared__ double red[kReduceThreads];
     const int si = active[blockIdx.x];
-    const double *p = partials + (int64_t)si * nblocks * OBS_NSUMS;
+    const double *p = partials + obs_off[si];
     for (int q = 0; q < OBS_NSUMS; ++q) {
         double acc = 0.0;
         for (int b = threadIdx.x; b < nblocks; b += kReduceThreads) acc += p[(int64_t)b * OBS_NSUMS + q];
@@ -265,7 +264,7 @@ hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const
 
 hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
                                     const ObsArgs<double> *args, int nx, int ny, double *partials,
-                                    double *sums, hipStream_t stream)
+                                    const int64_t *obs_off, double *sums, hipStream_t stream)
 {
     if (nact <= 0) return hipSuccess;
     const dim3 grid((unsigned)((nx + kObsX - 1) / kObsX), (unsigned)((ny + kObsY - 1) / kObsY),
@@ -273,14 +272,14 @@ hipError_t launch_observables_batch(bool c64, int nact, const int *active, void 
     const dim3 block(kObsX * kObsY);
     if (c64)
         hipLaunchKernelGGL(calcmuen_rms_batch_kernel<float2>, grid, block, 0, stream,
-                           reinterpret_cast<float2 *const *>(psis), active, args, partials);
+                           reinterpret_cast<float2 *const *>(psis), active, args, partials, obs_off);
     else
         hipLaunchKernelGGL(calcmuen_rms_batch_kernel<double2>, grid, block, 0, stream,
-                           reinterpret_cast<double2 *const *>(psis), active, args, partials);
+                           reinterpret_cast<double2 *const *>(psis), active, args, partials, obs_off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_finalize_batch_kernel, dim3((unsigned)nact), dim3(kReduceThreads), 0, stream,
-                       active, partials, (int)(grid.x * grid.y), sums);
+                       active, partials, obs_off, (int)(grid.x * grid.y), sums);
     return hipGetLastError();
 }
 

@@ -1,0 +1,181 @@
+"""The request server (gp_server_*): continuous batching of solves.
+
+A served solve runs the batched kernels with its events (mu checks, the end
+of a run) at multiples of check_every of its own steps, so its result must be
+bitwise that of a gp_plan stepped check_every steps per call with the same
+stopping rule -- alone, or admitted while other requests are resident.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1206_1361_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1206_1361_amd as gp  # noqa: E402
+from paper_1206_1361_amd._binding import ERR_NONFINITE  # noqa: E402
+
+K = 10
+
+
+def requests(seed=0, n=6, dtype=np.complex64):
+    """Mixed imaginary-time ground states and real-time quenches on three
+    grid shapes."""
+    rng = np.random.default_rng(seed)
+    shapes = [(24, 20, 16), (33, 17, 9), (40, 32, 24)]
+    out = []
+    for i in range(n):
+        grid = shapes[i % len(shapes)]
+        trap = tuple(float(v) for v in rng.uniform(0.5, 3.0, 3))
+        g = float(rng.uniform(1.0, 500.0))
+        real = i % 3 == 2
+        dx = 0.3
+        psi = inputs.gaussian(grid, (dx,) * 3, trap).astype(dtype)
+        out.append(dict(psi=psi, dx=dx, dt=(0.005 if real else 0.1) * dx * dx, trap=trap, g=g,
+                        mode="real" if real else "imag", steps=45 if real else 400,
+                        tol=0.0 if real else 1e-7))
+    return out
+
+
+def submit(srv, rq, tag):
+    return srv.submit(rq["psi"], dx=rq["dx"], dt=rq["dt"], trap=rq["trap"], g=rq["g"], mode=rq["mode"],
+                      steps=rq["steps"], tol=rq["tol"], tag=tag)
+
+
+def collect(srv, n, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < n:
+        for r in srv.poll(wait=1.0):
+            got[r["tag"]] = r
+        assert time.time() - t0 < timeout, f"only {len(got)} of {n} results"
+    return got
+
+
+def plan_reference(rq, dtype):
+    """The same solve on a single plan: K steps per call, |dmu| < tol stop."""
+    nz, ny, nx = rq["psi"].shape
+    psi = torch.from_numpy(rq["psi"].copy()).cuda()
+    with gp.Plan((nx, ny, nz), (rq["dx"],) * 3, rq["dt"], *rq["trap"], rq["g"], mode=rq["mode"],
+                 dtype=dtype) as p:
+        if rq["mode"] == "real":
+            p.step(psi, rq["steps"])
+            return psi.cpu().numpy(), p.observables(psi), rq["steps"], False
+        last = p.observables(psi)["mu"]
+        done = 0
+        while True:
+            k = min(K, rq["steps"] - done)
+            p.step(psi, k)
+            done += k
+            obs = p.observables(psi)
+            conv = rq["tol"] > 0 and abs(obs["mu"] - last) < rq["tol"]
+            if conv or done >= rq["steps"]:
+                return psi.cpu().numpy(), obs, done, conv
+            last = obs["mu"]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_served_results_equal_single_plans(dtype):
+    npd = np.complex64 if dtype == "c64" else np.complex128
+    rqs = requests(1, dtype=npd)
+    with gp.Server(dtype=dtype, hbm_budget=256 << 20, max_slots=16, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+        assert srv.drain(10.0)
+        st = srv.stats()
+    assert st["completed"] == len(rqs) and st["resident"] == 0 and st["bytes_in_use"] == 0
+    for i, rq in enumerate(rqs):
+        r = got[i]
+        ref, robs, steps, conv = plan_reference(rq, dtype)
+        assert r["status"] == 0
+        assert r["steps"] == steps and r["converged"] == conv, (i, r["steps"], steps)
+        assert np.array_equal(r["psi"], ref), i
+        assert r["obs"]["mu"] == robs["mu"] and r["obs"]["norm"] == robs["norm"], i
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_same_alone_and_in_the_mix():
+    """Each request served alone equals the same request served while others
+    arrive, run and leave around it (bitwise)."""
+    rqs = requests(2, n=9)
+    alone = {}
+    with gp.Server(dtype="c64", hbm_budget=256 << 20, max_slots=16, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+            alone.update(collect(srv, 1))
+    mix = {}
+    with gp.Server(dtype="c64", hbm_budget=256 << 20, max_slots=16, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+            if i % 3 == 1:
+                time.sleep(0.01)        # later arrivals join a running mix
+        mix = collect(srv, len(rqs))
+        assert srv.stats()["max_resident"] > 1
+    for i in range(len(rqs)):
+        assert alone[i]["status"] == 0 and mix[i]["status"] == 0
+        assert alone[i]["steps"] == mix[i]["steps"], i
+        assert np.array_equal(alone[i]["psi"], mix[i]["psi"]), i
+        assert alone[i]["obs"]["mu"] == mix[i]["obs"]["mu"], i
+
+
+def test_admission_by_footprint():
+    """A budget that holds two requests at a time: never more than two are
+    resident, every request completes, results unchanged."""
+    rqs = requests(3, n=6)
+    rqs = [dict(rq, psi=inputs.gaussian((40, 32, 24), (0.3,) * 3, rq["trap"]).astype(np.complex64))
+           for rq in rqs]
+    need = gp.request_bytes((40, 32, 24), "c64", "imag")
+    assert need >= 40 * 32 * 24 * 8
+    with gp.Server(dtype="c64", hbm_budget=2 * need + 1024, max_slots=16, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+        st = srv.stats()
+    assert st["max_resident"] == 2
+    assert st["bytes_peak"] <= st["bytes_budget"]
+    for i, rq in enumerate(rqs):
+        ref, robs, steps, conv = plan_reference(rq, "c64")
+        assert np.array_equal(got[i]["psi"], ref), i
+
+
+def test_slot_limit_and_graph_off():
+    rqs = requests(4, n=5)
+    with gp.Server(dtype="c64", hbm_budget=256 << 20, max_slots=1, check_every=K, graph=False) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+        assert srv.stats()["max_resident"] == 1
+    for i, rq in enumerate(rqs):
+        ref, _, _, _ = plan_reference(rq, "c64")
+        assert np.array_equal(got[i]["psi"], ref), i
+
+
+def test_zero_state_is_reported_not_fatal():
+    rqs = requests(5, n=3)
+    rqs[0] = dict(rqs[0], psi=np.zeros_like(rqs[0]["psi"]), mode="imag", tol=1e-7)
+    with gp.Server(dtype="c64", hbm_budget=256 << 20, max_slots=8, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+    assert got[0]["status"] == ERR_NONFINITE
+    for i in (1, 2):
+        assert got[i]["status"] == 0
+
+
+def test_submit_checks():
+    psi = inputs.gaussian((16, 16, 16), (0.3,) * 3, (1, 1, 1)).astype(np.complex64)
+    with gp.Server(dtype="c64", hbm_budget=1 << 20, max_slots=4, check_every=K) as srv:
+        with pytest.raises(ValueError):
+            srv.submit(psi.astype(np.complex128), dx=0.3, dt=0.01, trap=(1, 1, 1), g=1.0, steps=10)
+        with pytest.raises(gp.GPInvalid):
+            srv.submit(psi, dx=0.3, dt=-0.01, trap=(1, 1, 1), g=1.0, steps=10)
+        with pytest.raises(gp.GPInvalid):
+            srv.submit(psi, dx=0.3, dt=0.01, trap=(1, 1, 1), g=1.0, steps=0)
+        big = np.zeros((128, 128, 128), np.complex64)
+        with pytest.raises(gp.GPNoMemory):
+            srv.submit(big, dx=0.3, dt=0.01, trap=(1, 1, 1), g=1.0, steps=10)
+        assert srv.drain(5.0)

@@ -250,3 +250,16 @@ def test_batch_create_rejects_bad_arguments_before_any_device_call():
     assert L.gp_batch_destroy(None) == _binding.OK
     assert L.gp_batch_step(None, 1) == _binding.ERR_INVALID
     assert L.gp_batch_observables(None, None) == _binding.ERR_INVALID
+
+
+def test_server_request_bytes():
+    """Footprint used for admission: psi plus tables and reduction scratch,
+    256-byte blocks; imaginary time adds the per-line norm partials."""
+    psi = 40 * 32 * 24 * 8
+    imag = gp.request_bytes((40, 32, 24), "c64", "imag")
+    real = gp.request_bytes((40, 32, 24), "c64", "real")
+    assert imag % 256 == 0 and real % 256 == 0
+    assert psi < real < imag
+    assert imag - real >= 40 * 32 * 8
+    assert gp.request_bytes((40, 32, 24), "c128", "imag") > imag
+    assert gp.request_bytes((2000, 8, 8), "c64", "imag") == 0
