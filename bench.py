@@ -21,6 +21,10 @@ runs 256 uneven imaginary-time ground-state solves (grids 48^3 to 160^3,
 dx 0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between
 checks 10 steps apart) as one complex64 batch and, for comparison, one by
 one on complex128 plans, with the complex64 error at equal step counts.
+`serve` drives the request server with Poisson arrivals at 50/s of mixed
+ground-state and real-time requests (64^3 to 160x128x96) for a few seconds
+and reports p50/p99 latency and throughput (python -m
+paper_1206_1361_amd.serve runs the full 60 s).
 """
 from __future__ import annotations
 
@@ -268,6 +272,8 @@ def main() -> int:
                     help="solves in the batched imaginary-time comparison (0 skips it)")
     ap.add_argument("--batch-sample", type=int, default=32,
                     help="solves re-run in complex128 to the batch's step counts for the error figures")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals (50/s) in the serving leg (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB buffer three times with torch (a plain copy kernel "
                          "of known size, to scale hardware byte counters)")
@@ -335,6 +341,10 @@ def main() -> int:
         out["latency"] = latency(gp, torch, args.latency_repeats)
     if args.batch_solves > 0:
         out["batch"] = batch_bench(gp, torch, args.batch_solves, 1e-8, 10, 20000, args.batch_sample)
+    if args.serve_seconds > 0:
+        from paper_1206_1361_amd import serve
+
+        out["serve"] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype="c64", verify=4, log=log)
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(w, psi_host, args.cpu_seconds)

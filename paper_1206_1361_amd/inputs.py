@@ -48,6 +48,16 @@ def gaussian(grid, dx, omega) -> np.ndarray:
     return normalise(psi, dx)
 
 
+def separable_gaussian(grid, dx, omega, dtype=np.complex64) -> np.ndarray:
+    """The same normalised Gaussian as `gaussian`, built from three 1D
+    factors (outer products, no 3D exponential) in the requested dtype --
+    fast enough to make one per served request."""
+    f = [np.exp(-0.5 * w * axis(n, d) ** 2) for n, d, w in zip(grid, dx, omega)]
+    f = [v / math.sqrt(float(np.dot(v, v)) * d) for v, d in zip(f, dx)]
+    zy = np.multiply.outer(f[2], f[1])
+    return np.multiply.outer(zy, f[0]).astype(dtype)
+
+
 def mu_thomas_fermi(omega, g: float) -> float:
     """Thomas-Fermi chemical potential 1/2 (15 g gamma nu lambda / (4 pi))^(2/5)."""
     return 0.5 * (15.0 * g * omega[0] * omega[1] * omega[2] / (4.0 * math.pi)) ** 0.4
