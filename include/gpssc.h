@@ -50,9 +50,17 @@ typedef enum { GP_MODE_IMAG = 0, GP_MODE_REAL = 1 } gp_mode;
  *              the sweeps and the phase update.
  * GP_C64_F64 : psi is complex<float>  (8 B per point), FP64 arithmetic in
  *              registers (only the stored values are rounded to FP32).
+ * GP_R64     : psi is double (8 B per point), the real part only; FP64
+ *              arithmetic.  Imaginary time only: every imaginary-time
+ *              operator is real, so a real state stays real, and the step
+ *              does the GP_C128 arithmetic on its real part (y/z lines of up
+ *              to 256 points are cut into at most 32 chunks, so the rounding
+ *              order there differs from GP_C128's).
+ * GP_R32     : psi is float (4 B per point), real; FP32 arithmetic
+ *              (bitwise GP_C64 of the real state).  Imaginary time only.
  * Every reduction (norm, energy, chemical potential, rms sizes) is
- * accumulated in FP64 for all three. */
-typedef enum { GP_C128 = 0, GP_C64 = 1, GP_C64_F64 = 2 } gp_dtype;
+ * accumulated in FP64 for all of them. */
+typedef enum { GP_C128 = 0, GP_C64 = 1, GP_C64_F64 = 2, GP_R64 = 3, GP_R32 = 4 } gp_dtype;
 
 typedef enum {
     GP_OK = 0,

@@ -8,7 +8,7 @@ loaded on first use, so importing the package (or its seeded input
 generators in ``inputs``) needs no GPU.
 """
 from ._binding import (  # noqa: F401
-    C64, C64_F64, C128, IMAG, REAL, EXPORTS, KERNELS, Batch, GPError, GPInvalid, GPNoMemory, GPNonFinite,
+    C64, C64_F64, C128, IMAG, R32, R64, REAL, EXPORTS, KERNELS, Batch, GPError, GPInvalid, GPNoMemory, GPNonFinite,
     Plan, Server,
     footprint_bytes, lib, library_path, request_bytes, sweep_shape, sweep_tables,
 )

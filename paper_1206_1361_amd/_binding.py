@@ -18,6 +18,8 @@ REAL = 1
 C128 = 0
 C64 = 1
 C64_F64 = 2
+R64 = 3
+R32 = 4
 
 OK = 0
 ERR_INVALID = 1
@@ -208,6 +210,10 @@ def _dtype(dtype) -> int:
             return C64
         if dtype in (C64_F64, "c64_f64"):
             return C64_F64
+        if dtype in (R64, "r64", "float64"):
+            return R64
+        if dtype in (R32, "r32", "float32"):
+            return R32
         raise ValueError(f"unknown dtype {dtype!r}")
     import torch
 
@@ -215,7 +221,25 @@ def _dtype(dtype) -> int:
         return C128
     if dtype == torch.complex64:
         return C64
+    if dtype == torch.float64:
+        return R64
+    if dtype == torch.float32:
+        return R32
     raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def torch_dtype_of(dtype: int):
+    """Element type of psi tensors for a library dtype."""
+    import torch
+
+    return {C128: torch.complex128, C64: torch.complex64, C64_F64: torch.complex64, R64: torch.float64,
+            R32: torch.float32}[dtype]
+
+
+def numpy_dtype_of(dtype: int):
+    import numpy as np
+
+    return {C128: np.complex128, C64: np.complex64, C64_F64: np.complex64, R64: np.float64, R32: np.float32}[dtype]
 
 
 def footprint_bytes(grid, dtype="c128") -> int:
@@ -252,7 +276,8 @@ class Plan:
     """One grid, step size, trap, coupling, mode and dtype.
 
     psi tensors are torch.complex128 (dtype "c128") or torch.complex64
-    ("c64": FP32 arithmetic, "c64_f64": FP64 arithmetic on FP32 storage),
+    ("c64": FP32 arithmetic, "c64_f64": FP64 arithmetic on FP32 storage), or,
+    for imaginary time, real torch.float64 ("r64") or torch.float32 ("r32");
     CUDA (HIP) device, contiguous, shape (Nz, Ny, Nx).
     """
 
@@ -267,7 +292,7 @@ class Plan:
         self.g = float(g)
         self.mode = _mode(mode)
         self.dtype = _dtype(dtype)
-        self.torch_dtype = torch.complex128 if self.dtype == C128 else torch.complex64
+        self.torch_dtype = torch_dtype_of(self.dtype)
         self._handle = ctypes.c_void_p()
         n = (ctypes.c_int64 * 3)(*self.grid)
         d = (ctypes.c_double * 3)(*self.dx)
@@ -410,7 +435,7 @@ class Batch:
         self.grids = [tuple(int(v) for v in row) for row in grids]
         self.mode = _mode(mode)
         self.dtype = _dtype(dtype)
-        self.torch_dtype = torch.complex128 if self.dtype == C128 else torch.complex64
+        self.torch_dtype = torch_dtype_of(self.dtype)
         flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0)
         self._handle = ctypes.c_void_p()
         self._psis = None
@@ -513,7 +538,7 @@ class Server:
         global _servers
         L = lib()
         self.dtype = _dtype(dtype)
-        self.np_dtype = np.complex128 if self.dtype == C128 else np.complex64
+        self.np_dtype = numpy_dtype_of(self.dtype)
         self.check_every = int(check_every)
         self._handle = ctypes.c_void_p()
         self._held = {}

@@ -211,14 +211,14 @@ hipError_t build_graph(gp_batch *b)
 // block that runs fastest on this device, timed on scratch memory of one
 // solve's size (the choice does not change any result: each column's
 // arithmetic and its norm partial are independent of it).
-template <typename S>
 hipError_t tune_class(gp_batch *b, Class &c)
 {
     const Solve &x = b->s[(size_t)c.members[0]];
     void *scratch = nullptr;
-    hipError_t e = hipMalloc(&scratch, sizeof(S) * (size_t)x.elems);
+    const size_t bytes = storage_bytes(b->dtype) * (size_t)x.elems;
+    hipError_t e = hipMalloc(&scratch, bytes);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(scratch, 0, sizeof(S) * (size_t)x.elems, b->own);
+    e = hipMemsetAsync(scratch, 0, bytes, b->own);
     int *d_one = nullptr;
     void **d_ptr = nullptr;
     const int zero = 0;
@@ -309,6 +309,8 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         return fail(GP_ERR_INVALID, "need nsolves >= 1 and every parameter array");
     if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
     if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
+    if (real_storage(dtype) && mode != GP_MODE_IMAG)
+        return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
     if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE)) return fail(GP_ERR_INVALID, "unknown flags");
     for (int i = 0; i < nsolves; ++i) {
         if (!valid_grid(grids + 3 * i)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
@@ -381,8 +383,8 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         }                                                                             \
     } while (0)
     GB_ALLOC(b->d_tables, std::max<size_t>(tab_bytes, 16));
-    const size_t xs = dtype == GP_C64 ? sizeof(gpssc::XBatchArgs<float>) : sizeof(gpssc::XBatchArgs<double>);
-    const size_t ss = dtype == GP_C64 ? sizeof(gpssc::SBatchArgs<float>) : sizeof(gpssc::SBatchArgs<double>);
+    const size_t xs = arith_f32(dtype) ? sizeof(gpssc::XBatchArgs<float>) : sizeof(gpssc::XBatchArgs<double>);
+    const size_t ss = arith_f32(dtype) ? sizeof(gpssc::SBatchArgs<float>) : sizeof(gpssc::SBatchArgs<double>);
     GB_ALLOC(b->d_xargs, xs * (size_t)nsolves);
     GB_ALLOC(b->d_yargs, ss * (size_t)nsolves);
     GB_ALLOC(b->d_zargs, ss * (size_t)nsolves);
@@ -418,9 +420,9 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
         dvs[(size_t)i] = x.dx[0] * x.dx[1] * x.dx[2];
         oa[(size_t)i] = obs_args(x);
     }
-    std::vector<unsigned char> xa = dtype == GP_C64 ? pack_batch_args<float>(b, 0) : pack_batch_args<double>(b, 0);
-    std::vector<unsigned char> ya = dtype == GP_C64 ? pack_batch_args<float>(b, 1) : pack_batch_args<double>(b, 1);
-    std::vector<unsigned char> za = dtype == GP_C64 ? pack_batch_args<float>(b, 2) : pack_batch_args<double>(b, 2);
+    std::vector<unsigned char> xa = arith_f32(dtype) ? pack_batch_args<float>(b, 0) : pack_batch_args<double>(b, 0);
+    std::vector<unsigned char> ya = arith_f32(dtype) ? pack_batch_args<float>(b, 1) : pack_batch_args<double>(b, 1);
+    std::vector<unsigned char> za = arith_f32(dtype) ? pack_batch_args<float>(b, 2) : pack_batch_args<double>(b, 2);
     struct Up {
         void *dst;
         const void *src;
@@ -442,7 +444,7 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     if (e == hipSuccess) e = hipStreamSynchronize(b->own);
     if (e == hipSuccess && (flags & GP_BATCH_TUNE)) {
         for (Class &c : b->cls) {
-            e = dtype == GP_C128 ? tune_class<double2>(b, c) : tune_class<float2>(b, c);
+            e = tune_class(b, c);
             if (e != hipSuccess) break;
             class_tiles(c);
         }
@@ -472,7 +474,7 @@ gp_status gp_batch_set_psi(gp_batch *b, void *const *psi, const int64_t *elems)
     if (!b) return fail(GP_ERR_INVALID, "batch is NULL");
     if (!psi || !elems) return fail(GP_ERR_INVALID, "psi and elems arrays are required");
     DeviceGuard guard(b->device);
-    const uintptr_t align = b->dtype == GP_C128 ? 16 : 8;
+    const uintptr_t align = storage_bytes(b->dtype);
     for (int i = 0; i < b->n; ++i) {
         if (!psi[i]) return fail(GP_ERR_INVALID, "psi[" + std::to_string(i) + "] is NULL");
         if (elems[i] != b->s[(size_t)i].elems)
@@ -526,10 +528,9 @@ gp_status gp_batch_step(gp_batch *b, int64_t nsteps)
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
         e = use_graph ? hipGraphLaunch(b->exec, b->own) : enqueue_step(b);
     if (e == hipSuccess && b->mode == GP_MODE_IMAG) {
-        const bool c64 = b->dtype != GP_C128;
         for (const Class &c : b->cls) {
             if (!c.nact) continue;
-            e = gpssc::launch_scale_batch(c64, c.nact, c.d_active, b->d_psis, c.grid[0] * c.grid[1] * c.grid[2],
+            e = gpssc::launch_scale_batch(static_cast<gpssc::Prec>(b->dtype), c.nact, c.d_active, b->d_psis, c.grid[0] * c.grid[1] * c.grid[2],
                                           b->d_scales, b->own);
             if (e != hipSuccess) break;
         }
@@ -546,10 +547,9 @@ gp_status gp_batch_observables(gp_batch *b, gp_obs *out)
     if (!bound(b)) return fail(GP_ERR_INVALID, "bind psi with gp_batch_set_psi first");
     DeviceGuard guard(b->device);
     hipError_t e = sync_in(b);
-    const bool c64 = b->dtype != GP_C128;
     for (const Class &c : b->cls) {
         if (!c.nact || e != hipSuccess) continue;
-        e = gpssc::launch_observables_batch(c64, c.nact, c.d_active, b->d_psis, b->d_obsargs, (int)c.grid[0],
+        e = gpssc::launch_observables_batch(static_cast<gpssc::Prec>(b->dtype), c.nact, c.d_active, b->d_psis, b->d_obsargs, (int)c.grid[0],
                                             (int)c.grid[1], b->d_obs_partials, b->d_obs_off, b->d_sums, b->own);
     }
     if (e == hipSuccess)

@@ -44,23 +44,84 @@ __device__ __forceinline__ cx<A> cfma(cx<A> a, cx<A> b, cx<A> c)
 template <typename A>
 __device__ __forceinline__ A cabs2(cx<A> a) { return fma(a.re, a.re, a.im * a.im); }
 
-// Storage <-> arithmetic conversion.  psi is stored as double2 (complex128)
-// or float2 (complex64).
+// Storage <-> arithmetic conversion.  psi is stored as double2 (complex128),
+// float2 (complex64), or -- for imaginary-time states, which stay real when
+// they start real -- as double or float holding the real part only.  Values
+// are always handled as cx<A> in registers; a real element loads with a zero
+// imaginary part and stores its real part, so a real state runs exactly the
+// arithmetic of the complex state with zero imaginary parts.
 template <typename S> struct storage_traits;
-template <> struct storage_traits<double2> { using real = double; };
-template <> struct storage_traits<float2> { using real = float; };
+template <> struct storage_traits<double2> { using real = double; static constexpr bool complex = true; };
+template <> struct storage_traits<float2> { using real = float; static constexpr bool complex = true; };
+template <> struct storage_traits<double> { using real = double; static constexpr bool complex = false; };
+template <> struct storage_traits<float> { using real = float; static constexpr bool complex = false; };
 
 template <typename A, typename S>
-__device__ __forceinline__ cx<A> ld(S v) { return cx<A>{(A)v.x, (A)v.y}; }
+__device__ __forceinline__ cx<A> ld(S v)
+{
+    if constexpr (storage_traits<S>::complex)
+        return cx<A>{(A)v.x, (A)v.y};
+    else
+        return cx<A>{(A)v, (A)0};
+}
 
 template <typename S, typename A>
 __device__ __forceinline__ S st(cx<A> v)
 {
     using R = typename storage_traits<S>::real;
-    S r;
-    r.x = (R)v.re;
-    r.y = (R)v.im;
-    return r;
+    if constexpr (storage_traits<S>::complex) {
+        S r;
+        r.x = (R)v.re;
+        r.y = (R)v.im;
+        return r;
+    } else {
+        return (R)v.re;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ S szero()
+{
+    if constexpr (storage_traits<S>::complex) {
+        S r;
+        r.x = 0;
+        r.y = 0;
+        return r;
+    } else {
+        return (S)0;
+    }
+}
+
+// Real and imaginary part of a stored element, in FP64.
+template <typename S>
+__device__ __forceinline__ double sre(S v)
+{
+    if constexpr (storage_traits<S>::complex)
+        return (double)v.x;
+    else
+        return (double)v;
+}
+
+template <typename S>
+__device__ __forceinline__ double sim(S v)
+{
+    if constexpr (storage_traits<S>::complex)
+        return (double)v.y;
+    else
+        return 0.0;
+}
+
+// v * s componentwise in the storage precision.
+template <typename S>
+__device__ __forceinline__ S sscale(S v, typename storage_traits<S>::real s)
+{
+    if constexpr (storage_traits<S>::complex) {
+        v.x *= s;
+        v.y *= s;
+        return v;
+    } else {
+        return v * s;
+    }
 }
 
 // Constant-coefficient factorisation of one axis.  The Crank-Nicolson
@@ -98,29 +159,41 @@ template <> struct vec2_of<float2> { typedef float type __attribute__((ext_vecto
 template <typename S>
 __device__ __forceinline__ S stream_load(const S *p)
 {
-    typedef typename vec2_of<S>::type V;
-    V v;
-    if (GPSSC_NT_LOAD)
-        v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
-    else
-        v = *reinterpret_cast<const V *>(p);
-    S r;
-    r.x = v.x;
-    r.y = v.y;
-    return r;
+    if constexpr (storage_traits<S>::complex) {
+        typedef typename vec2_of<S>::type V;
+        V v;
+        if (GPSSC_NT_LOAD)
+            v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+        else
+            v = *reinterpret_cast<const V *>(p);
+        S r;
+        r.x = v.x;
+        r.y = v.y;
+        return r;
+    } else {
+        if (GPSSC_NT_LOAD) return __builtin_nontemporal_load(p);
+        return *p;
+    }
 }
 
 template <typename S>
 __device__ __forceinline__ void stream_store(S *p, S val)
 {
-    typedef typename vec2_of<S>::type V;
-    V v;
-    v.x = val.x;
-    v.y = val.y;
-    if (GPSSC_NT_STORE)
-        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
-    else
-        *reinterpret_cast<V *>(p) = v;
+    if constexpr (storage_traits<S>::complex) {
+        typedef typename vec2_of<S>::type V;
+        V v;
+        v.x = val.x;
+        v.y = val.y;
+        if (GPSSC_NT_STORE)
+            __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+        else
+            *reinterpret_cast<V *>(p) = v;
+    } else {
+        if (GPSSC_NT_STORE)
+            __builtin_nontemporal_store(val, p);
+        else
+            *p = val;
+    }
 }
 
 // Launch arguments of the calcnu + calclux kernel.
@@ -177,8 +250,9 @@ struct ObsArgs {
 // ---- host-side launchers (one translation unit per kernel family) ----
 
 // Precision of a launch: storage and arithmetic types (double2/double,
-// float2/float, float2/double).
-enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2 };
+// float2/float, float2/double, double/double, float/float).  The values
+// equal gp_dtype's.
+enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2, PREC_R64 = 3, PREC_R32 = 4 };
 
 // calcnu + calclux.  zt: boundary correction by position (complex, the
 // arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
@@ -201,13 +275,13 @@ hipError_t launch_norm_finalize(const double *partials, int n, double dv, double
                                 int *flag, hipStream_t stream);
 
 // psi <- psi * (*scale)
-hipError_t launch_scale(bool c64, void *psi, int64_t elems, const double *scale,
+hipError_t launch_scale(Prec prec, void *psi, int64_t elems, const double *scale,
                         hipStream_t stream);
 
 // calcmuen + calcrms raw sums: partials [nblocks][OBS_NSUMS] then a fixed
 // order final sum into sums[OBS_NSUMS].
 int obs_num_blocks(int nx, int ny);
-hipError_t launch_observables(bool c64, const void *psi, const ObsArgs<double> &args,
+hipError_t launch_observables(Prec prec, const void *psi, const ObsArgs<double> &args,
                               double *partials, double *sums, hipStream_t stream);
 
 // ---- batched launchers: one launch covers every active solve of one grid
@@ -231,12 +305,12 @@ hipError_t launch_norm_finalize_batch(int nact, const int *active, const double 
                                       double *scales, int *flags, hipStream_t stream);
 
 // psi_i <- psi_i * scales[i] for the active solves, then scales[i] <- 1.
-hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const *psis,
+hipError_t launch_scale_batch(Prec prec, int nact, const int *active, void *const *psis,
                               int64_t elems, double *scales, hipStream_t stream);
 
 // Observables sums per solve: sums[i * OBS_NSUMS + q].  partials + obs_off[i]:
 // solve i's obs_num_blocks(nx, ny) * OBS_NSUMS doubles of scratch.
-hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
+hipError_t launch_observables_batch(Prec prec, int nact, const int *active, void *const *psis,
                                     const ObsArgs<double> *args, int nx, int ny, double *partials,
                                     const int64_t *obs_off, double *sums, hipStream_t stream);
 

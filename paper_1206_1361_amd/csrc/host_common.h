@@ -39,7 +39,26 @@ inline gp_status fail_hip(hipError_t e, const char *what)
 inline const int kChunksX[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16};
 inline const int kChunksYZ[] = {1, 2, 4, 8, 16};
 
-inline int max_lanes_for(gp_dtype dtype) { return dtype == GP_C64 ? 32 : gpssc::kMaxLanesYZ; }
+// FP32 arithmetic: complex64 and real float storage.
+inline bool arith_f32(gp_dtype d) { return d == GP_C64 || d == GP_R32; }
+// Real storage (imaginary time only).
+inline bool real_storage(gp_dtype d) { return d == GP_R64 || d == GP_R32; }
+// Bytes of one stored element.
+inline size_t storage_bytes(gp_dtype d)
+{
+    return d == GP_C128 ? 16 : (d == GP_R32 ? 4 : 8);
+}
+
+// Most chunks per y/z line.  FP32 arithmetic affords 16-point chunks, so 32
+// chunks cover 512 points; real FP64 storage takes 32 chunks of at most 8
+// points on lines up to 256 (so blocks can hold 32 columns: 256-byte rows),
+// 64 chunks beyond; complex FP64 keeps 64 chunks of at most 8 points.
+inline int max_lanes_for(gp_dtype dtype, int64_t n)
+{
+    if (arith_f32(dtype)) return 32;
+    if (dtype == GP_R64 && n <= 8 * 32) return 32;
+    return gpssc::kMaxLanesYZ;
+}
 
 // Chunking of a line of n points along `axis`: chunk points per lane, lanes
 // per line.  Returns false when the line is longer than the kernels handle.
@@ -187,7 +206,10 @@ inline std::vector<unsigned char> pack_tables(const AxisTables ax[3], size_t off
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-inline bool valid_dtype(gp_dtype d) { return d == GP_C128 || d == GP_C64 || d == GP_C64_F64; }
+inline bool valid_dtype(gp_dtype d)
+{
+    return d == GP_C128 || d == GP_C64 || d == GP_C64_F64 || d == GP_R64 || d == GP_R32;
+}
 
 inline bool valid_grid(const int64_t grid[3])
 {

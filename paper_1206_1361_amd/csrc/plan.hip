@@ -133,8 +133,8 @@ size_t footprint(const int64_t grid[3], gp_dtype dtype, int *xt_y, int *xt_z)
 {
     int c[3], l[3];
     for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &c[a], &l[a], max_lanes_for(dtype))) return 0;
-    const size_t cs = dtype == GP_C64 ? 8 : 16;   // table entries: complex<float> or <double>
+        if (!sweep_shape(grid[a], a, &c[a], &l[a], max_lanes_for(dtype, grid[a]))) return 0;
+    const size_t cs = arith_f32(dtype) ? 8 : 16;   // table entries: complex<float> or <double>
     size_t tab = 0;
     for (int a = 0; a < 3; ++a) tab += (size_t)c[a] * l[a];
     tab *= cs;
@@ -173,7 +173,7 @@ gp_status check_psi(const gp_plan *p, const void *psi, int64_t elems)
     if (elems != want)
         return fail(GP_ERR_INVALID, "psi holds " + std::to_string(elems) + " elements, the grid needs " +
                                         std::to_string(want));
-    const uintptr_t align = p->dtype == GP_C128 ? 16 : 8;
+    const uintptr_t align = storage_bytes(p->dtype);
     if ((uintptr_t)psi % align != 0) return fail(GP_ERR_INVALID, "psi is misaligned");
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, psi);
@@ -230,8 +230,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     if (st != GP_OK) return st;
     if (nsteps == 0) return GP_OK;
     const gpssc::Prec prec = static_cast<gpssc::Prec>(p->dtype);
-    const bool c64 = p->dtype != GP_C128;   // complex64 storage
-    const bool a32 = p->dtype == GP_C64;    // FP32 arithmetic
+    const bool a32 = arith_f32(p->dtype);   // FP32 arithmetic
     const bool real = p->mode == GP_MODE_REAL;
     const void *xargs = a32 ? (const void *)&p->xf : (const void *)&p->xd;
     const void *yargs = a32 ? (const void *)&p->sf[0] : (const void *)&p->sd[0];
@@ -268,7 +267,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     if (e == hipSuccess && !real) {
         const int64_t elems = p->n[0] * p->n[1] * p->n[2];
         e = timed(p, GP_KERNEL_SCALE,
-                  [&] { return gpssc::launch_scale(c64, psi, elems, p->d_scale, p->stream); });
+                  [&] { return gpssc::launch_scale(prec, psi, elems, p->d_scale, p->stream); });
     }
     if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
     p->steps_done += nsteps;
@@ -299,7 +298,7 @@ gp_status gp_sweep_shape(int64_t n, int axis, gp_dtype dtype, int *chunk, int *l
     if (!chunk || !lanes || axis < 0 || axis > 2 || !valid_dtype(dtype))
         return fail(GP_ERR_INVALID, "bad gp_sweep_shape arguments");
     if (n < 1) return fail(GP_ERR_INVALID, "line length must be >= 1");
-    if (!sweep_shape(n, axis, chunk, lanes, max_lanes_for(dtype))) return fail(GP_ERR_UNSUPPORTED, "line too long");
+    if (!sweep_shape(n, axis, chunk, lanes, max_lanes_for(dtype, n))) return fail(GP_ERR_UNSUPPORTED, "line too long");
     return GP_OK;
 }
 
@@ -353,9 +352,11 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
     if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
     if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
+    if (real_storage(dtype) && mode != GP_MODE_IMAG)
+        return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
     int chunk[3], lanes[3];
     for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a], max_lanes_for(dtype)))
+        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a], max_lanes_for(dtype, grid[a])))
             return fail(GP_ERR_UNSUPPORTED, "grid line too long (Nx <= 1024, Ny, Nz <= 1024)");
     if (grid[1] * grid[2] > 0x7fffffffLL || grid[1] > 65535 || grid[2] > 65535)
         return fail(GP_ERR_UNSUPPORTED, "too many grid lines for one launch");
@@ -381,7 +382,7 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
     const bool real = mode == GP_MODE_REAL;
     for (int a = 0; a < 3; ++a) build_axis(grid[a], dx[a], dt, real, chunk[a], lanes[a], p->ax[a]);
     footprint(grid, dtype, &p->xt_y, &p->xt_z);
-    std::vector<unsigned char> tab = dtype == GP_C64 ? pack_tables<float>(p->ax, p->tab_off)
+    std::vector<unsigned char> tab = arith_f32(dtype) ? pack_tables<float>(p->ax, p->tab_off)
                                                      : pack_tables<double>(p->ax, p->tab_off);
     p->n_zblocks = (int)(grid[0] * grid[1]);   // one norm partial per z line
     p->n_obs_blocks = gpssc::obs_num_blocks((int)grid[0], (int)grid[1]);
@@ -520,7 +521,7 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
     a.hgy = 0.5 * p->omega[1] * p->omega[1];
     a.hgz = 0.5 * p->omega[2] * p->omega[2];
     hipError_t e = timed(p, GP_KERNEL_OBS, [&] {
-        return gpssc::launch_observables(p->dtype != GP_C128, psi, a, p->d_obs_partials, p->d_sums,
+        return gpssc::launch_observables(static_cast<gpssc::Prec>(p->dtype), psi, a, p->d_obs_partials, p->d_sums,
                                          p->stream);
     });
     if (e == hipSuccess)
@@ -565,7 +566,7 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
 gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
 {
     if (!p || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_plan_describe arguments");
-    const bool a32 = p->dtype == GP_C64;
+    const bool a32 = arith_f32(p->dtype);
     int nst[3], nzc[3];
     const gpssc::SweepCoef<double> *kd[3] = {&p->xd.k, &p->sd[0].k, &p->sd[1].k};
     const gpssc::SweepCoef<float> *kf[3] = {&p->xf.k, &p->sf[0].k, &p->sf[1].k};
@@ -573,7 +574,8 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
         nst[a] = a32 ? kf[a]->nst : kd[a]->nst;
         nzc[a] = a32 ? kf[a]->nzc : kd[a]->nzc;
     }
-    const char *dt = p->dtype == GP_C64 ? "c64" : (p->dtype == GP_C64_F64 ? "c64/f64" : "c128");
+    const char *names[] = {"c128", "c64", "c64/f64", "r64", "r32"};
+    const char *dt = names[(int)p->dtype];
     std::snprintf(buf, len,
                   "grid %lldx%lldx%lld %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
                   "%d blocks | y: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks | "

@@ -78,10 +78,7 @@ scale_batch_kernel(S *const *__restrict__ psis, const int *__restrict__ active, 
     S *psi = psis[si];
     const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
     for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
-        S v = psi[p];
-        v.x *= s;
-        v.y *= s;
-        psi[p] = v;
+        psi[p] = sscale(psi[p], s);
     }
 }
 
@@ -99,10 +96,7 @@ scale_kernel(S *__restrict__ psi, int64_t elems, const double *__restrict__ scal
     const R s = (R)(*scale);
     const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
     for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
-        S v = psi[p];
-        v.x *= s;
-        v.y *= s;
-        psi[p] = v;
+        psi[p] = sscale(psi[p], s);
     }
 }
 
@@ -125,6 +119,9 @@ __device__ __forceinline__ void obs_block(const S *__restrict__ psi, const ObsAr
     for (int q = 0; q < OBS_NSUMS; ++q) acc[q] = 0.0;
 
     if (i < a.nx && j < a.ny) {
+        // every product and sum rounded on its own (no fused multiply-add),
+        // so the sums do not depend on whether the storage is complex or real
+#pragma clang fp contract(off)
         const int64_t plane = (int64_t)a.nx * a.ny;
         const double x = ((double)i - a.c0x) * a.dx;
         const double y = ((double)j - a.c0y) * a.dy;
@@ -133,7 +130,7 @@ __device__ __forceinline__ void obs_block(const S *__restrict__ psi, const ObsAr
         const S *col = psi + (int64_t)j * a.nx + i;
         for (int k = 0; k < a.nz; ++k) {
             const S v = col[(int64_t)k * plane];
-            const double re = v.x, im = v.y;
+            const double re = sre(v), im = sim(v);
             const double w = re * re + im * im;
             const double z = ((double)k - a.c0z) * a.dz;
             acc[OBS_DENS] += w;
@@ -149,8 +146,8 @@ __device__ __forceinline__ void obs_block(const S *__restrict__ psi, const ObsAr
             double nre = 0.0, nim = 0.0;
             if (i + 1 < a.nx) {
                 const S n = col[(int64_t)k * plane + 1];
-                nre = n.x;
-                nim = n.y;
+                nre = sre(n);
+                nim = sim(n);
             }
             acc[OBS_LINKX] += (nre - re) * (nre - re) + (nim - im) * (nim - im);
             if (i == 0) acc[OBS_LINKX] += w;
@@ -159,8 +156,8 @@ __device__ __forceinline__ void obs_block(const S *__restrict__ psi, const ObsAr
             nim = 0.0;
             if (j + 1 < a.ny) {
                 const S n = col[(int64_t)k * plane + a.nx];
-                nre = n.x;
-                nim = n.y;
+                nre = sre(n);
+                nim = sim(n);
             }
             acc[OBS_LINKY] += (nre - re) * (nre - re) + (nim - im) * (nim - im);
             if (j == 0) acc[OBS_LINKY] += w;
@@ -232,6 +229,21 @@ obs_finalize_batch_kernel(const int *__restrict__ active, const double *__restri
     }
 }
 
+// Calls f with a value of the storage type of prec (the type selects the
+// kernel instantiation).
+template <typename F>
+hipError_t with_storage(Prec prec, F f)
+{
+    switch (prec) {
+    case PREC_C128: return f(double2{});
+    case PREC_C64:
+    case PREC_C64_F64: return f(float2{});
+    case PREC_R64: return f(double{});
+    case PREC_R32: return f(float{});
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_norm_finalize_batch(int nact, const int *active, const double *partials,
                                       const int64_t *part_off, int ntiles, const double *dv,
                                       double *scales, int *flags, hipStream_t stream)
@@ -242,7 +254,7 @@ hipError_t launch_norm_finalize_batch(int nact, const int *active, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const *psis, int64_t elems,
+hipError_t launch_scale_batch(Prec prec, int nact, const int *active, void *const *psis, int64_t elems,
                               double *scales, hipStream_t stream)
 {
     if (nact <= 0) return hipSuccess;
@@ -250,19 +262,18 @@ hipError_t launch_scale_batch(bool c64, int nact, const int *active, void *const
     if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
     const dim3 grid((unsigned)blocks, (unsigned)nact);
-    if (c64)
-        hipLaunchKernelGGL(scale_batch_kernel<float2>, grid, dim3(kReduceThreads), 0, stream,
-                           reinterpret_cast<float2 *const *>(psis), active, elems, scales);
-    else
-        hipLaunchKernelGGL(scale_batch_kernel<double2>, grid, dim3(kReduceThreads), 0, stream,
-                           reinterpret_cast<double2 *const *>(psis), active, elems, scales);
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_storage(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL(scale_batch_kernel<S>, grid, dim3(kReduceThreads), 0, stream,
+                           reinterpret_cast<S *const *>(psis), active, elems, scales);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_scales_kernel, dim3(1), dim3(kReduceThreads), 0, stream, active, nact, scales);
     return hipGetLastError();
 }
 
-hipError_t launch_observables_batch(bool c64, int nact, const int *active, void *const *psis,
+hipError_t launch_observables_batch(Prec prec, int nact, const int *active, void *const *psis,
                                     const ObsArgs<double> *args, int nx, int ny, double *partials,
                                     const int64_t *obs_off, double *sums, hipStream_t stream)
 {
@@ -270,13 +281,12 @@ hipError_t launch_observables_batch(bool c64, int nact, const int *active, void 
     const dim3 grid((unsigned)((nx + kObsX - 1) / kObsX), (unsigned)((ny + kObsY - 1) / kObsY),
                     (unsigned)nact);
     const dim3 block(kObsX * kObsY);
-    if (c64)
-        hipLaunchKernelGGL(calcmuen_rms_batch_kernel<float2>, grid, block, 0, stream,
-                           reinterpret_cast<float2 *const *>(psis), active, args, partials, obs_off);
-    else
-        hipLaunchKernelGGL(calcmuen_rms_batch_kernel<double2>, grid, block, 0, stream,
-                           reinterpret_cast<double2 *const *>(psis), active, args, partials, obs_off);
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_storage(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL(calcmuen_rms_batch_kernel<S>, grid, block, 0, stream,
+                           reinterpret_cast<S *const *>(psis), active, args, partials, obs_off);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_finalize_batch_kernel, dim3((unsigned)nact), dim3(kReduceThreads), 0, stream,
                        active, partials, obs_off, (int)(grid.x * grid.y), sums);
@@ -291,19 +301,18 @@ hipError_t launch_norm_finalize(const double *partials, int n, double dv, double
     return hipGetLastError();
 }
 
-hipError_t launch_scale(bool c64, void *psi, int64_t elems, const double *scale,
+hipError_t launch_scale(Prec prec, void *psi, int64_t elems, const double *scale,
                         hipStream_t stream)
 {
     int64_t blocks = (elems + kReduceThreads - 1) / kReduceThreads;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    if (c64)
-        hipLaunchKernelGGL(scale_kernel<float2>, dim3((unsigned)blocks), dim3(kReduceThreads), 0,
-                           stream, static_cast<float2 *>(psi), elems, scale);
-    else
-        hipLaunchKernelGGL(scale_kernel<double2>, dim3((unsigned)blocks), dim3(kReduceThreads), 0,
-                           stream, static_cast<double2 *>(psi), elems, scale);
-    return hipGetLastError();
+    return with_storage(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL(scale_kernel<S>, dim3((unsigned)blocks), dim3(kReduceThreads), 0, stream,
+                           static_cast<S *>(psi), elems, scale);
+        return hipGetLastError();
+    });
 }
 
 int obs_num_blocks(int nx, int ny)
@@ -311,19 +320,18 @@ int obs_num_blocks(int nx, int ny)
     return ((nx + kObsX - 1) / kObsX) * ((ny + kObsY - 1) / kObsY);
 }
 
-hipError_t launch_observables(bool c64, const void *psi, const ObsArgs<double> &args,
+hipError_t launch_observables(Prec prec, const void *psi, const ObsArgs<double> &args,
                               double *partials, double *sums, hipStream_t stream)
 {
     const dim3 grid((unsigned)((args.nx + kObsX - 1) / kObsX),
                     (unsigned)((args.ny + kObsY - 1) / kObsY));
     const dim3 block(kObsX * kObsY);
-    if (c64)
-        hipLaunchKernelGGL(calcmuen_rms_kernel<float2>, grid, block, 0, stream,
-                           static_cast<const float2 *>(psi), args, partials);
-    else
-        hipLaunchKernelGGL(calcmuen_rms_kernel<double2>, grid, block, 0, stream,
-                           static_cast<const double2 *>(psi), args, partials);
-    hipError_t e = hipGetLastError();
+    hipError_t e = with_storage(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL(calcmuen_rms_kernel<S>, grid, block, 0, stream, static_cast<const S *>(psi), args,
+                           partials);
+        return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(obs_finalize_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
                        partials, (int)grid.x * (int)grid.y, sums);

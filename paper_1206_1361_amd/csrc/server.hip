@@ -376,7 +376,7 @@ hipError_t capture(gp_server *S)
 // Observables sums of the listed slots of one class into sums (per slot).
 hipError_t observe(gp_server *S, const SClass &c, int n, const int *d_slots, double *sums)
 {
-    return gpssc::launch_observables_batch(S->dtype != GP_C128, n, d_slots, S->d_psis, S->d_obsargs,
+    return gpssc::launch_observables_batch(static_cast<gpssc::Prec>(S->dtype), n, d_slots, S->d_psis, S->d_obsargs,
                                            (int)c.grid[0], (int)c.grid[1], reinterpret_cast<double *>(S->d_arena),
                                            S->d_obs_off, sums, S->stream);
 }
@@ -514,7 +514,7 @@ bool round_once(gp_server *S)
         build_solve(L.d, c);
         L.slot = S->free_slots.back();
         S->free_slots.pop_back();
-        e = S->dtype == GP_C64 ? stage_solve<float>(S, L, c, f) : stage_solve<double>(S, L, c, f);
+        e = arith_f32(S->dtype) ? stage_solve<float>(S, L, c, f) : stage_solve<double>(S, L, c, f);
         if (e != hipSuccess) {
             fail_all(S, e, "copying a request in");
             return false;
@@ -568,7 +568,7 @@ bool round_once(gp_server *S)
         e = hipMemcpyAsync(c.d_due, c.h_stage + 2 * ms, sizeof(int) * (size_t)c.ndue, hipMemcpyHostToDevice,
                            S->stream);
         if (e == hipSuccess && !c.real)
-            e = gpssc::launch_scale_batch(S->dtype != GP_C128, c.ndue, c.d_due, S->d_psis,
+            e = gpssc::launch_scale_batch(static_cast<gpssc::Prec>(S->dtype), c.ndue, c.d_due, S->d_psis,
                                           c.grid[0] * c.grid[1] * c.grid[2], S->d_scales, S->stream);
         if (e == hipSuccess) e = observe(S, c, c.ndue, c.d_due, S->d_sums);
     }
@@ -665,8 +665,8 @@ gp_status gp_server_create(gp_dtype dtype, uint64_t hbm_budget, int max_slots, i
     S->K = check_every;
     S->flags = flags;
     S->t0 = std::chrono::steady_clock::now();
-    S->xsz = dtype == GP_C64 ? sizeof(gpssc::XBatchArgs<float>) : sizeof(gpssc::XBatchArgs<double>);
-    S->ssz = dtype == GP_C64 ? sizeof(gpssc::SBatchArgs<float>) : sizeof(gpssc::SBatchArgs<double>);
+    S->xsz = arith_f32(dtype) ? sizeof(gpssc::XBatchArgs<float>) : sizeof(gpssc::XBatchArgs<double>);
+    S->ssz = arith_f32(dtype) ? sizeof(gpssc::SBatchArgs<float>) : sizeof(gpssc::SBatchArgs<double>);
     const size_t m = (size_t)max_slots;
     hipError_t e = hipGetDevice(&S->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
@@ -754,6 +754,8 @@ gp_status gp_server_submit(gp_server *S, const gp_request *r, uint64_t *id)
     if (r->steps < 1) return fail(GP_ERR_INVALID, "steps must be >= 1");
     if (!std::isfinite(r->tol) || r->tol < 0.0) return fail(GP_ERR_INVALID, "tol must be finite and >= 0");
     if (!r->psi_in || !r->psi_out) return fail(GP_ERR_INVALID, "psi_in and psi_out are required");
+    if (real_storage(S->dtype) && r->mode != GP_MODE_IMAG)
+        return fail(GP_ERR_INVALID, "a server with real storage takes imaginary-time requests only");
     if (!grid_supported(r->grid, S->dtype)) return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
     const size_t need = gp_server_request_bytes(r->grid, S->dtype, r->mode);
     std::lock_guard<std::mutex> lk(S->mu);

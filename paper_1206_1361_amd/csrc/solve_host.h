@@ -49,7 +49,7 @@ inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
     ClassShape c;
     for (int a = 0; a < 3; ++a) {
         c.grid[a] = grid[a];
-        sweep_shape(grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype));
+        sweep_shape(grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype, grid[a]));
     }
     c.xt_y = strided_columns(c.grid[0], c.lanes[1]);
     c.xt_z = strided_columns(c.grid[0], c.lanes[2]);
@@ -61,12 +61,11 @@ inline bool grid_supported(const int64_t grid[3], gp_dtype dtype)
 {
     int c, l;
     for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &c, &l, max_lanes_for(dtype))) return false;
+        if (!sweep_shape(grid[a], a, &c, &l, max_lanes_for(dtype, grid[a]))) return false;
     return true;
 }
 
-inline size_t complex_bytes(gp_dtype dtype) { return dtype == GP_C64 ? sizeof(cx<float>) : sizeof(cx<double>); }
-inline size_t storage_bytes(gp_dtype dtype) { return dtype == GP_C128 ? 16 : 8; }
+inline size_t complex_bytes(gp_dtype dtype) { return arith_f32(dtype) ? sizeof(cx<float>) : sizeof(cx<double>); }
 
 // Bytes of the three correction tables of a solve (chunk * lanes entries per
 // axis, in the arithmetic type).
@@ -92,7 +91,7 @@ inline void pack_solve_tables(const SolveDesc &x, const ClassShape &c, gp_dtype 
     size_t off = 0;
     for (int a = 0; a < 3; ++a) {
         for (int64_t q = 0; q < x.grid[a]; ++q) {
-            if (dtype == GP_C64) {
+            if (arith_f32(dtype)) {
                 const cx<float> v = to_cx<float>(x.ax[a].zt[(size_t)q]);
                 std::memcpy(dst + off + (size_t)q * sizeof v, &v, sizeof v);
             } else {

@@ -124,8 +124,7 @@ __device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row,
 #pragma unroll
     for (int r = 0; r < C; ++r) {
         const int e = r * kWave + lane;
-        v[r].x = 0;
-        v[r].y = 0;
+        v[r] = szero<S>();
         if (e < nx) v[r] = stream_load(row + e);
     }
 }
@@ -207,6 +206,7 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
                              const void *args, const int *active, const double *scales,
                              hipStream_t stream)
 {
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
     if (nact <= 0) return hipSuccess;
 #define GP_XB_PREC(S, A)                                                                      \
     return real ? launch_batch_c<S, A, true>(chunk, nact, nlines, psis, args, active, scales, stream) \
@@ -215,6 +215,8 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
     case PREC_C64: GP_XB_PREC(float2, float)
     case PREC_C64_F64: GP_XB_PREC(float2, double)
     case PREC_C128: GP_XB_PREC(double2, double)
+    case PREC_R64: GP_XB_PREC(double, double)
+    case PREC_R32: GP_XB_PREC(float, float)
     }
 #undef GP_XB_PREC
     return hipErrorInvalidValue;
@@ -249,6 +251,7 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
                        const void *zt, const double *scale, hipStream_t stream)
 {
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
 #define GP_X_PREC(S, A)                                                                   \
     return real ? launch_c<S, A, true>(chunk, nblocks, psi, args, zt, scale, stream)       \
                 : launch_c<S, A, false>(chunk, nblocks, psi, args, zt, scale, stream);
@@ -256,6 +259,8 @@ hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, 
     case PREC_C64: GP_X_PREC(float2, float)
     case PREC_C64_F64: GP_X_PREC(float2, double)
     case PREC_C128: GP_X_PREC(double2, double)
+    case PREC_R64: GP_X_PREC(double, double)
+    case PREC_R32: GP_X_PREC(float, float)
     }
 #undef GP_X_PREC
     return hipErrorInvalidValue;

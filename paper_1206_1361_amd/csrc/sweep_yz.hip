@@ -121,8 +121,11 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             if (act && pos0 + c < a.n) {
+                // rounded term by term (no fused multiply-add), the same for
+                // complex and real storage
+#pragma clang fp contract(off)
                 const S v = st<S>(u[c]);
-                acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                acc += sre(v) * sre(v) + sim(v) * sim(v);
             }
         }
         __syncthreads();  // LDS reuse
@@ -206,6 +209,7 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lan
                                 const int *active, double *partials, const int64_t *part_off,
                                 hipStream_t stream)
 {
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
     if (nact <= 0) return hipSuccess;
 #define GP_SB_PREC(S, A)                                                                              \
     return real ? launch_batch_t<S, A, true>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, \
@@ -216,6 +220,8 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lan
     case PREC_C64: GP_SB_PREC(float2, float)
     case PREC_C64_F64: GP_SB_PREC(float2, double)
     case PREC_C128: GP_SB_PREC(double2, double)
+    case PREC_R64: GP_SB_PREC(double, double)
+    case PREC_R32: GP_SB_PREC(float, float)
     }
 #undef GP_SB_PREC
     return hipErrorInvalidValue;
@@ -257,6 +263,7 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, i
                           void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream)
 {
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
 #define GP_S_PREC(S, A)                                                                           \
     return real ? launch_t<S, A, true>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream) \
                 : launch_t<S, A, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
@@ -264,6 +271,8 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, i
     case PREC_C64: GP_S_PREC(float2, float)
     case PREC_C64_F64: GP_S_PREC(float2, double)
     case PREC_C128: GP_S_PREC(double2, double)
+    case PREC_R64: GP_S_PREC(double, double)
+    case PREC_R32: GP_S_PREC(float, float)
     }
 #undef GP_S_PREC
     return hipErrorInvalidValue;

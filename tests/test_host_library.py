@@ -46,7 +46,8 @@ def test_status_strings_and_last_error():
 BAD_CREATE = [
     dict(grid=(0, 4, 4)), dict(grid=(4, -1, 4)), dict(dx=(0.1, 0.0, 0.1)), dict(dx=(0.1, float("nan"), 0.1)),
     dict(dt=0.0), dict(dt=-1.0), dict(dt=float("inf")), dict(gamma=-1.0), dict(lam=float("nan")),
-    dict(g=float("inf")), dict(mode=7), dict(dtype=3),
+    dict(g=float("inf")), dict(mode=7), dict(dtype=7),
+    dict(dtype=3, mode=1), dict(dtype=4, mode=1),     # real storage is imaginary time only
 ]
 
 
@@ -101,6 +102,12 @@ def test_sweep_shapes(n):
         assert c * l >= n and l <= 64 and (l - 1) * c < n
     with pytest.raises(gp.GPError):
         gp.sweep_shape(2048, 1)
+    # FP32 arithmetic, and real FP64 storage on lines up to 256, cut lines
+    # into at most 32 chunks (of at most 16, resp. 8 points)
+    for dt in ("c64", "r32", "r64"):
+        if n <= (512 if dt != "r64" else 256):
+            c, l = gp.sweep_shape(n, 1, dt)
+            assert l <= 32 and c * l >= n and c <= (16 if dt != "r64" else 8)
 
 
 def dense_cn_rhs_solve(n, tab, psi):
@@ -247,6 +254,8 @@ def test_batch_create_rejects_bad_arguments_before_any_device_call():
     assert create(mode=5) == (_binding.ERR_INVALID, None)
     assert create(flags=8) == (_binding.ERR_INVALID, None)
     assert create(grids=[8, 8, 8, 8, 2000, 8]) == (_binding.ERR_UNSUPPORTED, None)
+    assert create(dtype=3, mode=1) == (_binding.ERR_INVALID, None)
+    assert create(dtype=9) == (_binding.ERR_INVALID, None)
     assert L.gp_batch_destroy(None) == _binding.OK
     assert L.gp_batch_step(None, 1) == _binding.ERR_INVALID
     assert L.gp_batch_observables(None, None) == _binding.ERR_INVALID
@@ -263,3 +272,6 @@ def test_server_request_bytes():
     assert imag - real >= 40 * 32 * 8
     assert gp.request_bytes((40, 32, 24), "c128", "imag") > imag
     assert gp.request_bytes((2000, 8, 8), "c64", "imag") == 0
+    r64 = gp.request_bytes((40, 32, 24), "r64", "imag")
+    r32 = gp.request_bytes((40, 32, 24), "r32", "imag")
+    assert 40 * 32 * 24 * 4 < r32 < r64 < gp.request_bytes((40, 32, 24), "c128", "imag")
