@@ -178,10 +178,19 @@ def _solve_plan(gp, torch, sp, psi, dtype, tol, check_every, max_steps):
     return obs, done, False
 
 
+BATCH_FORMS = {
+    # name: (storage dtype, torch element type name, arithmetic)
+    "c64": ("complex64", "f32"),
+    "r64": ("float64", "f64"),
+    "r32": ("float32", "f32"),
+}
+
+
 def batch_bench(gp, torch, nsolves: int, tol: float, check_every: int, max_steps: int, sample: int) -> dict:
-    """Many uneven imaginary-time solves: the complex64 batch (FP64 reductions,
-    graph replay, tuned launch shapes, per-solve stopping) against the same
-    solves run one by one on complex128 plans with the same stopping rule."""
+    """Many uneven imaginary-time solves: batched forms (graph replay, tuned
+    launch shapes, per-solve stopping, FP64 reductions) against the same
+    solves run one by one on complex128 plans with the same stopping rule.
+    The starts are real Gaussians, so the real-storage forms apply."""
     from paper_1206_1361_amd import inputs
 
     specs = inputs.batch_imag_specs(nsolves)
@@ -191,19 +200,9 @@ def batch_bench(gp, torch, nsolves: int, tol: float, check_every: int, max_steps
         classes[key] = classes.get(key, 0) + 1
     start = lambda sp: inputs.gaussian(sp["grid"], (sp["dx"],) * 3, sp["trap"])  # noqa: E731
     pts = [int(np.prod(sp["grid"])) for sp in specs]
+    idx = list(range(0, nsolves, max(1, nsolves // sample)))[:sample]
 
-    log(f"[bench] batch: {nsolves} complex64 solves {classes}")
-    psis = [torch.from_numpy(start(sp)).to(torch.complex64).cuda() for sp in specs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with gp.Batch(specs, mode="imag", dtype="c64", graph=True, tune=True) as b:
-        b.bind(psis)
-        obs32, steps32, conv32 = b.solve_imag(tol=tol, check_every=check_every, max_steps=max_steps)
-    torch.cuda.synchronize()
-    t32 = time.perf_counter() - t0
-    log(f"[bench] batch: complex64 batch {t32:.2f} s, {sum(conv32)}/{nsolves} converged")
-
-    log("[bench] batch: the same solves one by one on complex128 plans")
+    log("[bench] batch: the solves one by one on complex128 plans")
     t64 = 0.0
     obs64, steps64, conv64 = [], [], []
     for sp in specs:
@@ -219,40 +218,57 @@ def batch_bench(gp, torch, nsolves: int, tol: float, check_every: int, max_steps
         del psi
     log(f"[bench] batch: complex128 one by one {t64:.2f} s, {sum(conv64)}/{nsolves} converged")
 
-    # precision alone: complex128 plans run to the batch's own step counts
-    idx = list(range(0, nsolves, max(1, nsolves // sample)))[:sample]
-    mu_err, psi_err = [], []
-    for i in idx:
-        sp = specs[i]
-        psi = torch.from_numpy(start(sp)).cuda()
-        with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode="imag", dtype="c128") as p:
-            for _ in range(steps32[i] // check_every):
-                p.step(psi, check_every)
-            p.step(psi, steps32[i] % check_every)
-            mu = p.observables(psi)["mu"]
-        mu_err.append(abs(obs32[i]["mu"] - mu) / abs(mu))
-        ref = psi.abs().max().item()
-        psi_err.append((psis[i].to(torch.complex128) - psi).abs().max().item() / ref)
-        del psi
-    stop_err = [abs(obs32[i]["mu"] - obs64[i]["mu"]) / abs(obs64[i]["mu"]) for i in range(nsolves)]
+    forms = {}
+    for name, (tname, arith) in BATCH_FORMS.items():
+        tdt = getattr(torch, tname)
+        log(f"[bench] batch: {nsolves} solves as one {name} batch {classes}")
+        real = not tdt.is_complex
+        psis = [torch.from_numpy(start(sp).real.copy() if real else start(sp)).to(tdt).cuda() for sp in specs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with gp.Batch(specs, mode="imag", dtype=name, graph=True, tune=True) as b:
+            b.bind(psis)
+            obs, steps, conv = b.solve_imag(tol=tol, check_every=check_every, max_steps=max_steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        log(f"[bench] batch: {name} {tb:.2f} s, {sum(conv)}/{nsolves} converged")
+        # precision alone: complex128 plans run to this batch's step counts
+        mu_err, psi_err = [], []
+        for i in idx:
+            sp = specs[i]
+            psi = torch.from_numpy(start(sp)).cuda()
+            with gp.Plan(sp["grid"], (sp["dx"],) * 3, sp["dt"], *sp["trap"], sp["g"], mode="imag",
+                         dtype="c128") as p:
+                for _ in range(steps[i] // check_every):
+                    p.step(psi, check_every)
+                p.step(psi, steps[i] % check_every)
+                mu = p.observables(psi)["mu"]
+            mu_err.append(abs(obs[i]["mu"] - mu) / abs(mu))
+            ref = psi.abs().max().item()
+            psi_err.append((psis[i].to(torch.complex128) - psi).abs().max().item() / ref)
+            del psi
+        stop_err = [abs(obs[i]["mu"] - obs64[i]["mu"]) / abs(obs64[i]["mu"]) for i in range(nsolves)]
+        forms[name] = {
+            "storage": tname, "arithmetic": arith, "reductions": "f64",
+            "seconds": round(tb, 3), "solves_per_s": round(nsolves / tb, 2), "converged": int(sum(conv)),
+            "steps_total": int(sum(steps)), "pt_steps_per_s": sum(p * s for p, s in zip(pts, steps)) / tb,
+            "speedup_vs_fp64_per_solve": round(t64 / tb, 3),
+            "accuracy": {"sample": f"{len(idx)} solves, complex128 plans run to the batch's step counts",
+                         "mu_rel_max": max(mu_err), "mu_rel_median": float(np.median(mu_err)),
+                         "psi_rel_max": max(psi_err),
+                         "mu_rel_max_vs_fp64_own_stop": max(stop_err),
+                         "mu_rel_median_vs_fp64_own_stop": float(np.median(stop_err))},
+        }
+        del psis
     return {
         "workload": f"imag-batch-{nsolves}", "solves": nsolves, "classes": classes,
         "dx": specs[0]["dx"], "dt": specs[0]["dt"], "stop": f"|dmu| < {tol:g} between checks {check_every} steps apart",
         "max_steps": max_steps,
-        "fp32_batched": {"storage": "complex64", "arithmetic": "f32", "reductions": "f64",
-                         "seconds": round(t32, 3), "solves_per_s": round(nsolves / t32, 2),
-                         "converged": int(sum(conv32)), "steps_total": int(sum(steps32)),
-                         "pt_steps_per_s": sum(p * s for p, s in zip(pts, steps32)) / t32},
         "fp64_per_solve": {"storage": "complex128", "arithmetic": "f64", "reductions": "f64",
                            "seconds": round(t64, 3), "solves_per_s": round(nsolves / t64, 2),
                            "converged": int(sum(conv64)), "steps_total": int(sum(steps64)),
                            "pt_steps_per_s": sum(p * s for p, s in zip(pts, steps64)) / t64},
-        "speedup": round(t64 / t32, 3),
-        "accuracy": {"sample": f"{len(idx)} solves, complex128 plans run to the batch's step counts",
-                     "mu_rel_max": max(mu_err), "mu_rel_median": float(np.median(mu_err)),
-                     "psi_rel_max": max(psi_err),
-                     "mu_rel_max_vs_fp64_own_stop": max(stop_err),
-                     "mu_rel_median_vs_fp64_own_stop": float(np.median(stop_err))},
+        "batched": forms,
     }
 
 
