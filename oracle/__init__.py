@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
                                   dp, ctypes.c_int]
         L.gpo_observables.argtypes = [i64p, dp, dp, ctypes.c_double, dp, dp]
         L.gpo_norm.argtypes = [i64p, dp, dp, dp]
+        L.gpo_step_nd.argtypes = [ctypes.c_int] + L.gpo_step.argtypes
+        L.gpo_observables_nd.argtypes = [ctypes.c_int] + L.gpo_observables.argtypes
+        L.gpo_norm_nd.argtypes = [ctypes.c_int] + L.gpo_norm.argtypes
         L.gpo_thomas.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, dp, dp]
         L.gpo_coord.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_int64]
@@ -93,7 +96,7 @@ def lib() -> ctypes.CDLL:
         L.gpo_set_threads.argtypes = [ctypes.c_int]
         L.gpo_get_threads.restype = ctypes.c_int
         for f in (L.gpo_validate, L.gpo_step, L.gpo_substep, L.gpo_observables,
-                  L.gpo_norm, L.gpo_thomas):
+                  L.gpo_norm, L.gpo_thomas, L.gpo_step_nd, L.gpo_observables_nd, L.gpo_norm_nd):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -128,10 +131,13 @@ def validate(grid, dx, dt, omega, g, mode) -> int:
     return int(lib().gpo_validate(n, d, float(dt), w, float(g), int(mode)))
 
 
-def step(psi: np.ndarray, dx, dt: float, omega, g: float, mode: int, nsteps: int = 1) -> np.ndarray:
-    """Advance psi in place by ``nsteps`` SSCN steps; returns psi."""
+def step(psi: np.ndarray, dx, dt: float, omega, g: float, mode: int, nsteps: int = 1,
+         ndim: int = 3) -> np.ndarray:
+    """Advance psi in place by ``nsteps`` SSCN steps; returns psi.  ndim 1 or
+    2: the equation in x (and y) only; psi then has shape (1, 1, Nx) or
+    (1, Ny, Nx)."""
     n, d, w = _grid_args(psi, dx, omega)
-    st = lib().gpo_step(n, d, float(dt), w, float(g), int(mode), _ptr(psi), int(nsteps))
+    st = lib().gpo_step_nd(int(ndim), n, d, float(dt), w, float(g), int(mode), _ptr(psi), int(nsteps))
     if st != OK:
         raise OracleError(st, "step")
     return psi
@@ -146,19 +152,19 @@ def substep(psi: np.ndarray, which: str, dx, dt: float, omega, g: float, mode: i
     return psi
 
 
-def norm(psi: np.ndarray, dx) -> float:
+def norm(psi: np.ndarray, dx, ndim: int = 3) -> float:
     n, d, _ = _grid_args(psi, dx)
     out = ctypes.c_double()
-    st = lib().gpo_norm(n, d, _ptr(psi), ctypes.byref(out))
+    st = lib().gpo_norm_nd(int(ndim), n, d, _ptr(psi), ctypes.byref(out))
     if st != OK:
         raise OracleError(st, "norm")
     return out.value
 
 
-def observables(psi: np.ndarray, dx, omega, g: float) -> dict:
+def observables(psi: np.ndarray, dx, omega, g: float, ndim: int = 3) -> dict:
     n, d, w = _grid_args(psi, dx, omega)
     out = (ctypes.c_double * len(OBS_NAMES))()
-    st = lib().gpo_observables(n, d, w, float(g), _ptr(psi), out)
+    st = lib().gpo_observables_nd(int(ndim), n, d, w, float(g), _ptr(psi), out)
     if st != OK:
         raise OracleError(st, "observables")
     return {k: out[i] for i, k in enumerate(OBS_NAMES)}

@@ -45,6 +45,16 @@
  *              rms_a = sqrt(dV sum a^2 |psi|^2 / N), rms_r = |(rms_a)|,
  *              mean_a = dV sum a |psi|^2 / N.
  *
+ * Fewer space variables (program summaries (i) imagtime1d, (ii) imagtime2d,
+ * (x) realtime1d and (xi) realtime2d; "Nature of problem": one, two or three
+ * space dimensions).  The _nd entry points take ndim = 1 (x) or 2 (x, y);
+ * the absent axes have one node and no part in the equation: no sweep along
+ * them, no trap term or kinetic links for them, and the cell volume dV is
+ * the product of the present spacings only.  So the ndim-dimensional
+ * equation is the one above with the Laplacian, V and the sums restricted
+ * to the present variables (reading: g is the coupling of that equation as
+ * given, no conversion from three dimensions).
+ *
  * Sums over the grid are formed per z plane in index order and then over the
  * planes in index order, so the result does not depend on the thread count.
  */
@@ -99,6 +109,23 @@ int gpo_validate(const int64_t n[3], const double dx[3], double dt,
                  const double omega[3], double g, int mode)
 {
     return valid_params(n, dx, dt, omega, g, mode) ? GPO_OK : GPO_ERR_INVALID;
+}
+
+/* ndim in 1..3, and one node along every absent axis. */
+static int valid_ndim(int ndim, const int64_t n[3])
+{
+    if (ndim < 1 || ndim > 3 || !n) return 0;
+    for (int a = ndim; a < 3; ++a)
+        if (n[a] != 1) return 0;
+    return 1;
+}
+
+/* Cell volume of the present axes. */
+static double cell_volume(int ndim, const double dx[3])
+{
+    double v = 1.0;
+    for (int a = 0; a < ndim; ++a) v *= dx[a];
+    return v;
 }
 
 /* Grid node coordinate along one axis: symmetric about the origin. */
@@ -297,22 +324,27 @@ static double sum_density(const int64_t n[3], const cplx *psi, double *plane)
     return s;
 }
 
-int gpo_norm(const int64_t n[3], const double dx[3], const double *psi_ri,
-             double *norm_out)
+int gpo_norm_nd(int ndim, const int64_t n[3], const double dx[3], const double *psi_ri,
+                double *norm_out)
 {
-    if (!n || !dx || !psi_ri || !norm_out) return GPO_ERR_INVALID;
+    if (!valid_ndim(ndim, n) || !dx || !psi_ri || !norm_out) return GPO_ERR_INVALID;
     double *plane = malloc(sizeof(double) * (size_t)n[2]);
     if (!plane) return GPO_ERR_NOMEM;
-    *norm_out = dx[0] * dx[1] * dx[2] * sum_density(n, (const cplx *)psi_ri, plane);
+    *norm_out = cell_volume(ndim, dx) * sum_density(n, (const cplx *)psi_ri, plane);
     free(plane);
     return GPO_OK;
 }
 
-static int calcnorm(const int64_t n[3], const double dx[3], cplx *psi,
-                    double *plane)
+int gpo_norm(const int64_t n[3], const double dx[3], const double *psi_ri,
+             double *norm_out)
+{
+    return gpo_norm_nd(3, n, dx, psi_ri, norm_out);
+}
+
+static int calcnorm(const int64_t n[3], double dv, cplx *psi, double *plane)
 {
     const int64_t total = n[0] * n[1] * n[2];
-    double norm = dx[0] * dx[1] * dx[2] * sum_density(n, psi, plane);
+    double norm = dv * sum_density(n, psi, plane);
     if (!(norm > 0.0) || !isfinite(norm)) return GPO_ERR_NONFINITE;
     double s = 1.0 / sqrt(norm);
 #pragma omp parallel for schedule(static)
@@ -324,25 +356,33 @@ static int calcnorm(const int64_t n[3], const double dx[3], cplx *psi,
 /* one SSCN step, repeated                                             */
 /* ------------------------------------------------------------------ */
 
-int gpo_step(const int64_t n[3], const double dx[3], double dt,
-             const double omega[3], double g, int mode, double *psi_ri,
-             int64_t nsteps)
+int gpo_step_nd(int ndim, const int64_t n[3], const double dx[3], double dt,
+                const double omega[3], double g, int mode, double *psi_ri,
+                int64_t nsteps)
 {
-    if (!valid_params(n, dx, dt, omega, g, mode) || !psi_ri || nsteps < 0)
+    if (!valid_params(n, dx, dt, omega, g, mode) || !valid_ndim(ndim, n) || !psi_ri || nsteps < 0)
         return GPO_ERR_INVALID;
     cplx *psi = (cplx *)psi_ri;
+    double om[3];
+    for (int a = 0; a < 3; ++a) om[a] = a < ndim ? omega[a] : 0.0;   /* no trap along absent axes */
+    const double dv = cell_volume(ndim, dx);
     double *plane = malloc(sizeof(double) * (size_t)n[2]);
     if (!plane) return GPO_ERR_NOMEM;
     int st = GPO_OK;
     for (int64_t s = 0; s < nsteps && st == GPO_OK; ++s) {
-        calcnu(n, dx, dt, omega, g, mode, psi);
-        st = calclu(n, dx, dt, mode, 0, psi);
-        if (st == GPO_OK) st = calclu(n, dx, dt, mode, 1, psi);
-        if (st == GPO_OK) st = calclu(n, dx, dt, mode, 2, psi);
-        if (st == GPO_OK && mode == GPO_IMAG) st = calcnorm(n, dx, psi, plane);
+        calcnu(n, dx, dt, om, g, mode, psi);
+        for (int a = 0; a < ndim && st == GPO_OK; ++a) st = calclu(n, dx, dt, mode, a, psi);
+        if (st == GPO_OK && mode == GPO_IMAG) st = calcnorm(n, dv, psi, plane);
     }
     free(plane);
     return st;
+}
+
+int gpo_step(const int64_t n[3], const double dx[3], double dt,
+             const double omega[3], double g, int mode, double *psi_ri,
+             int64_t nsteps)
+{
+    return gpo_step_nd(3, n, dx, dt, omega, g, mode, psi_ri, nsteps);
 }
 
 /* Single sub-steps, so that tests can check each against an independent
@@ -360,7 +400,7 @@ int gpo_substep(const int64_t n[3], const double dx[3], double dt,
     case 4: {
         double *plane = malloc(sizeof(double) * (size_t)n[2]);
         if (!plane) return GPO_ERR_NOMEM;
-        int st = calcnorm(n, dx, psi, plane);
+        int st = calcnorm(n, dx[0] * dx[1] * dx[2], psi, plane);
         free(plane);
         return st;
     }
@@ -377,11 +417,13 @@ typedef struct {
     double dens, pot, quart, link[3], m1[3], m2[3];
 } plane_sums;
 
-int gpo_observables(const int64_t n[3], const double dx[3],
-                    const double omega[3], double g, const double *psi_ri,
-                    double *out)
+int gpo_observables_nd(int ndim, const int64_t n[3], const double dx[3],
+                       const double omega[3], double g, const double *psi_ri,
+                       double *out)
 {
-    if (!n || !dx || !omega || !psi_ri || !out) return GPO_ERR_INVALID;
+    if (!n || !dx || !omega || !psi_ri || !out || !valid_ndim(ndim, n)) return GPO_ERR_INVALID;
+    double om[3];
+    for (int a = 0; a < 3; ++a) om[a] = a < ndim ? omega[a] : 0.0;
     for (int a = 0; a < 3; ++a)
         if (n[a] < 1 || !(dx[a] > 0.0)) return GPO_ERR_INVALID;
     const cplx *psi = (const cplx *)psi_ri;
@@ -402,7 +444,7 @@ int gpo_observables(const int64_t n[3], const double dx[3],
                 cplx v = psi[p];
                 double w = creal(v) * creal(v) + cimag(v) * cimag(v);
                 s.dens += w;
-                s.pot += potential(omega, x, y, z) * w;
+                s.pot += potential(om, x, y, z) * w;
                 s.quart += w * w;
                 s.m1[0] += x * w; s.m1[1] += y * w; s.m1[2] += z * w;
                 s.m2[0] += x * x * w; s.m2[1] += y * y * w; s.m2[2] += z * z * w;
@@ -435,13 +477,13 @@ int gpo_observables(const int64_t n[3], const double dx[3],
     }
     free(ps);
 
-    const double dv = dx[0] * dx[1] * dx[2];
+    const double dv = cell_volume(ndim, dx);
     const double norm = dv * t.dens;
     for (int q = 0; q < GPO_OBS_COUNT; ++q) out[q] = NAN;
     out[GPO_OBS_NORM] = norm;
     if (!(norm > 0.0) || !isfinite(norm)) return GPO_ERR_NONFINITE;
     double kin = 0.0;
-    for (int a = 0; a < 3; ++a) kin += t.link[a] / (dx[a] * dx[a]);
+    for (int a = 0; a < ndim; ++a) kin += t.link[a] / (dx[a] * dx[a]);
     kin *= 0.5 * dv;
     const double pot = dv * t.pot;
     const double inter = g * dv * t.quart;
@@ -461,4 +503,11 @@ int gpo_observables(const int64_t n[3], const double dx[3],
     for (int q = 0; q < GPO_OBS_COUNT; ++q)
         if (!isfinite(out[q])) return GPO_ERR_NONFINITE;
     return GPO_OK;
+}
+
+int gpo_observables(const int64_t n[3], const double dx[3],
+                    const double omega[3], double g, const double *psi_ri,
+                    double *out)
+{
+    return gpo_observables_nd(3, n, dx, omega, g, psi_ri, out);
 }
