@@ -94,7 +94,7 @@ typedef struct {
 enum {
     GP_KERNEL_NU_X = 0,     /* calcnu + calclux (+ pending renormalisation) */
     GP_KERNEL_Y = 1,        /* calcluy */
-    GP_KERNEL_Z = 2,        /* calcluz (+ per-block norm partial sums in imaginary time) */
+    GP_KERNEL_Z = 2,        /* calcluz (+ per-line norm partial sums in imaginary time) */
     GP_KERNEL_NORM = 3,     /* calcnorm: partial sums -> 1/sqrt(N) on the device */
     GP_KERNEL_SCALE = 4,    /* end-of-call psi <- psi / sqrt(N) */
     GP_KERNEL_OBS = 5,      /* calcmuen + calcrms sums and their finalisation */
@@ -119,6 +119,20 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt,
                          double gamma, double nu, double lambda, double g,
                          gp_mode mode, gp_dtype dtype, void *hip_stream,
                          gp_plan **out);
+
+/* The equation in fewer space variables (the paper's one- and
+ * two-dimensional programs, summaries (i), (ii), (x), (xi)): ndim = 1 (x) or
+ * 2 (x, y); ndim = 3 is gp_plan_create.  Axes a >= ndim must have grid[a] = 1
+ * and take no part: no sweep along them, no trap term (their frequency is
+ * ignored), no kinetic links; the cell volume of the norm and of every
+ * observable is the product of the present spacings, and g is the coupling
+ * of the reduced equation as given.  psi keeps the (Nz, Ny, Nx) layout with
+ * the absent extents 1.  GP_ERR_INVALID for ndim outside 1..3 or an absent
+ * axis with more than one node; otherwise as gp_plan_create. */
+gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3], double dt,
+                            double gamma, double nu, double lambda, double g,
+                            gp_mode mode, gp_dtype dtype, void *hip_stream,
+                            gp_plan **out);
 
 /* Frees the plan's tables and scratch after waiting for its stream.
  * NULL-safe. */

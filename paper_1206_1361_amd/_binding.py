@@ -32,7 +32,7 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 
 # Every symbol include/gpssc.h declares.
 EXPORTS = (
-    "gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
+    "gp_plan_create", "gp_plan_create_nd", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
     "gp_step_schedule", "gp_sync",
     "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
@@ -131,6 +131,8 @@ def lib() -> ctypes.CDLL:
     ip = ctypes.POINTER(ctypes.c_int)
     L.gp_plan_create.argtypes = [i64p, dp, dbl, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int, vp,
                                  ctypes.POINTER(vp)]
+    L.gp_plan_create_nd.argtypes = [ctypes.c_int] + L.gp_plan_create.argtypes
+    L.gp_plan_create_nd.restype = ctypes.c_int
     L.gp_plan_destroy.argtypes = [vp]
     L.gp_set_g.argtypes = [vp, dbl]
     L.gp_set_trap.argtypes = [vp, dbl, dbl, dbl]
@@ -278,10 +280,11 @@ class Plan:
     psi tensors are torch.complex128 (dtype "c128") or torch.complex64
     ("c64": FP32 arithmetic, "c64_f64": FP64 arithmetic on FP32 storage), or,
     for imaginary time, real torch.float64 ("r64") or torch.float32 ("r32");
-    CUDA (HIP) device, contiguous, shape (Nz, Ny, Nx).
+    CUDA (HIP) device, contiguous, shape (Nz, Ny, Nx).  ndim = 1 or 2 solves
+    the equation in x (and y) only, on a grid with Nz = 1 (and Ny = 1).
     """
 
-    def __init__(self, grid, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", stream=None):
+    def __init__(self, grid, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", stream=None, ndim=3):
         import torch
 
         L = lib()
@@ -296,9 +299,10 @@ class Plan:
         self._handle = ctypes.c_void_p()
         n = (ctypes.c_int64 * 3)(*self.grid)
         d = (ctypes.c_double * 3)(*self.dx)
-        _check(L.gp_plan_create(n, d, self.dt, *self.omega, self.g, self.mode, self.dtype,
-                                self._stream_handle(stream), ctypes.byref(self._handle)),
-               "gp_plan_create")
+        self.ndim = int(ndim)
+        _check(L.gp_plan_create_nd(self.ndim, n, d, self.dt, *self.omega, self.g, self.mode, self.dtype,
+                                   self._stream_handle(stream), ctypes.byref(self._handle)),
+               "gp_plan_create_nd")
 
     @staticmethod
     def _stream_handle(stream):

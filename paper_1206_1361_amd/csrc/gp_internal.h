@@ -256,10 +256,11 @@ enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2, PREC_R64 = 3, PREC_R3
 
 // calcnu + calclux.  zt: boundary correction by position (complex, the
 // arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
+// partials: NULL or one double per x line (sum |psi|^2 of its output).
 // nblocks: one-wavefront blocks to launch (each loops over lines; 0 or >= the
 // line count = one per line).
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
-                       const void *zt, const double *scale, hipStream_t stream);
+                       const void *zt, const double *scale, double *partials, hipStream_t stream);
 
 // calcluy / calcluz over ceil(nx/xt) x nouter tiles.  nblocks: blocks to
 // launch (each loops over tiles; 0 or >= the tile count = one per tile).

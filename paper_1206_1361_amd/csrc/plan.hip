@@ -37,6 +37,7 @@ struct ProfRec {
 }  // namespace
 
 struct gp_plan {
+    int ndim = 3;        // space variables: x (1), x and y (2), or all three
     int64_t n[3];
     double dx[3];
     double dt, omega[3], g;
@@ -209,8 +210,10 @@ void set_g(gp_plan *p, double g)
     p->xf.g = (float)g;
 }
 
-void set_trap(gp_plan *p, const double om[3])
+void set_trap(gp_plan *p, const double om_in[3])
 {
+    double om[3];
+    for (int a = 0; a < 3; ++a) om[a] = a < p->ndim ? om_in[a] : 0.0;   // no trap along absent axes
     for (int a = 0; a < 3; ++a) p->omega[a] = om[a];
     p->xd.hgx = 0.5 * om[0] * om[0];
     p->xd.hgy = 0.5 * om[1] * om[1];
@@ -236,7 +239,13 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     const void *yargs = a32 ? (const void *)&p->sf[0] : (const void *)&p->sd[0];
     const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
     const unsigned char *T = p->d_tables;
-    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
+    const int nd = p->ndim;
+    double dv = 1.0;
+    for (int a = 0; a < nd; ++a) dv *= p->dx[a];
+    // the last sweep leaves the norm partials, one per line along its axis
+    double *parts = real ? nullptr : p->d_partials;
+    const int nparts = nd == 3 ? (int)(p->n[0] * p->n[1]) : (nd == 2 ? (int)(p->n[0] * p->n[2])
+                                                                       : (int)(p->n[1] * p->n[2]));
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
         if (g_steps) set_g(p, g_steps[s]);
@@ -244,24 +253,26 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
         e = timed(p, GP_KERNEL_NU_X, [&] {
             return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
-                                      T + p->tab_off[0], scale, p->stream);
+                                      T + p->tab_off[0], scale, nd == 1 ? parts : nullptr, p->stream);
         });
         if (e != hipSuccess) break;
-        e = timed(p, GP_KERNEL_Y, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
-                                         p->y_blocks, psi, yargs, T + p->tab_off[1], nullptr,
-                                         p->stream);
-        });
-        if (e != hipSuccess) break;
-        e = timed(p, GP_KERNEL_Z, [&] {
-            return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
-                                         p->z_blocks, psi, zargs, T + p->tab_off[2],
-                                         real ? nullptr : p->d_partials, p->stream);
-        });
+        if (nd >= 2) {
+            e = timed(p, GP_KERNEL_Y, [&] {
+                return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
+                                             p->y_blocks, psi, yargs, T + p->tab_off[1],
+                                             nd == 2 ? parts : nullptr, p->stream);
+            });
+            if (e != hipSuccess) break;
+        }
+        if (nd == 3) {
+            e = timed(p, GP_KERNEL_Z, [&] {
+                return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
+                                             p->z_blocks, psi, zargs, T + p->tab_off[2], parts, p->stream);
+            });
+        }
         if (e != hipSuccess || real) continue;
         e = timed(p, GP_KERNEL_NORM, [&] {
-            return gpssc::launch_norm_finalize(p->d_partials, p->n_zblocks, dv, p->d_scale,
-                                               p->d_flag, p->stream);
+            return gpssc::launch_norm_finalize(p->d_partials, nparts, dv, p->d_scale, p->d_flag, p->stream);
         });
     }
     if (e == hipSuccess && !real) {
@@ -340,9 +351,19 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
                          double nu, double lambda, double g, gp_mode mode, gp_dtype dtype,
                          void *hip_stream, gp_plan **out)
 {
+    return gp_plan_create_nd(3, grid, dx, dt, gamma, nu, lambda, g, mode, dtype, hip_stream, out);
+}
+
+gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3], double dt, double gamma,
+                            double nu, double lambda, double g, gp_mode mode, gp_dtype dtype,
+                            void *hip_stream, gp_plan **out)
+{
     if (!out) return fail(GP_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!valid_grid(grid)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
+    if (ndim < 1 || ndim > 3) return fail(GP_ERR_INVALID, "ndim must be 1, 2 or 3");
+    for (int a = ndim; a < 3; ++a)
+        if (grid[a] != 1) return fail(GP_ERR_INVALID, "axes beyond ndim must have one node");
     if (!dx || !finite_pos(dx[0]) || !finite_pos(dx[1]) || !finite_pos(dx[2]))
         return fail(GP_ERR_INVALID, "dx must be finite and > 0");
     if (!finite_pos(dt)) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
@@ -363,10 +384,11 @@ gp_status gp_plan_create(const int64_t grid[3], const double dx[3], double dt, d
 
     gp_plan *p = new (std::nothrow) gp_plan();
     if (!p) return fail(GP_ERR_NOMEM, "host allocation failed");
+    p->ndim = ndim;
     for (int a = 0; a < 3; ++a) {
         p->n[a] = grid[a];
         p->dx[a] = dx[a];
-        p->omega[a] = om[a];
+        p->omega[a] = a < ndim ? om[a] : 0.0;   // no trap along absent axes
     }
     p->dt = dt;
     p->g = g;
@@ -531,11 +553,14 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
     if (e != hipSuccess) return fail_hip(e, "computing observables");
 
     const double *S = p->h_sums;
-    const double dv = p->dx[0] * p->dx[1] * p->dx[2];
+    // present axes only: their cell volume and their kinetic links
+    double dv = 1.0, links = 0.0;
+    for (int q = 0; q < p->ndim; ++q) {
+        dv *= p->dx[q];
+        links += S[gpssc::OBS_LINKX + q] / (p->dx[q] * p->dx[q]);
+    }
     const double norm = dv * S[gpssc::OBS_DENS];
-    const double kin = 0.5 * dv *
-                       (S[gpssc::OBS_LINKX] / (p->dx[0] * p->dx[0]) + S[gpssc::OBS_LINKY] / (p->dx[1] * p->dx[1]) +
-                        S[gpssc::OBS_LINKZ] / (p->dx[2] * p->dx[2]));
+    const double kin = 0.5 * dv * links;
     const double pot = dv * S[gpssc::OBS_POT];
     const double inter = p->g * dv * S[gpssc::OBS_QUART];
     out->norm = norm;
@@ -577,10 +602,10 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     const char *names[] = {"c128", "c64", "c64/f64", "r64", "r32"};
     const char *dt = names[(int)p->dtype];
     std::snprintf(buf, len,
-                  "grid %lldx%lldx%lld %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
+                  "grid %lldx%lldx%lld %dD %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
                   "%d blocks | y: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks | "
                   "z: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks",
-                  (long long)p->n[0], (long long)p->n[1], (long long)p->n[2],
+                  (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->ndim,
                   p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
                   p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->y_blocks,
                   p->ax[2].chunk, p->ax[2].lanes, p->xt_z, nst[2], nzc[2], p->z_blocks);

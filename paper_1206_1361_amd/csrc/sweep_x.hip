@@ -131,10 +131,13 @@ __device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row,
 
 // One wavefront per block; block b solves lines b, b + G, ... (G =
 // gridDim.x).  The plan launches one block per line.
+// partials: NULL, or one double per line receiving sum |psi|^2 of the stored
+// line (the norm partials of imaginary time when x is the only variable),
+// summed per lane in row order, then over the lanes by a fixed tree.
 template <typename S, typename A, int C, bool REAL>
 __global__ void __launch_bounds__(kWave)
 calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict__ zt,
-                  const double *__restrict__ scale)
+                  const double *__restrict__ scale, double *__restrict__ partials)
 {
     __shared__ S buf[kWave * C + kWave];
     const int lane = threadIdx.x;
@@ -149,6 +152,19 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
         for (int r = 0; r < C; ++r) {
             const int e = r * kWave + lane;
             if (e < a.nx) stream_store(row + e, v[r]);
+        }
+        if (partials) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < C; ++r) {
+                if (r * kWave + lane < a.nx) {
+#pragma clang fp contract(off)
+                    acc += sre(v[r]) * sre(v[r]) + sim(v[r]) * sim(v[r]);
+                }
+            }
+#pragma unroll
+            for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_down(acc, d, kWave);
+            if (lane == 0) partials[line] = acc;
         }
         __syncthreads();  // buf is free for the next line
     }
@@ -224,7 +240,7 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
 
 template <typename S, typename A, bool REAL>
 static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, const void *zt,
-                           const double *scale, hipStream_t stream)
+                           const double *scale, double *partials, hipStream_t stream)
 {
     const XArgs<A> &a = *static_cast<const XArgs<A> *>(args);
     const int nlines = a.ny * a.nz;
@@ -235,7 +251,7 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
 #define GP_X_CASE(CC)                                                                  \
     case CC:                                                                           \
         hipLaunchKernelGGL((calcnu_lux_kernel<S, A, CC, REAL>), grid, block, 0, stream, \
-                           p, a, z, scale);                                            \
+                           p, a, z, scale, partials);                                  \
         break;
     switch (chunk) {
         GP_X_CASE(1) GP_X_CASE(2) GP_X_CASE(3) GP_X_CASE(4)
@@ -249,12 +265,12 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
 }
 
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
-                       const void *zt, const double *scale, hipStream_t stream)
+                       const void *zt, const double *scale, double *partials, hipStream_t stream)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
 #define GP_X_PREC(S, A)                                                                   \
-    return real ? launch_c<S, A, true>(chunk, nblocks, psi, args, zt, scale, stream)       \
-                : launch_c<S, A, false>(chunk, nblocks, psi, args, zt, scale, stream);
+    return real ? launch_c<S, A, true>(chunk, nblocks, psi, args, zt, scale, partials, stream)  \
+                : launch_c<S, A, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
     switch (prec) {
     case PREC_C64: GP_X_PREC(float2, float)
     case PREC_C64_F64: GP_X_PREC(float2, double)

@@ -275,3 +275,14 @@ def test_server_request_bytes():
     r64 = gp.request_bytes((40, 32, 24), "r64", "imag")
     r32 = gp.request_bytes((40, 32, 24), "r32", "imag")
     assert 40 * 32 * 24 * 4 < r32 < r64 < gp.request_bytes((40, 32, 24), "c128", "imag")
+
+
+def test_plan_create_nd_rejects_bad_shapes_before_any_device_call():
+    L = gp.lib()
+    d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    for ndim, grid in ((0, (8, 1, 1)), (4, (8, 8, 8)), (2, (8, 8, 2)), (1, (8, 2, 1)), (1, (8, 1, 3))):
+        n = (ctypes.c_int64 * 3)(*grid)
+        out = ctypes.c_void_p(5)
+        assert L.gp_plan_create_nd(ndim, n, d, 0.01, 1.0, 1.0, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == \
+            _binding.ERR_INVALID, (ndim, grid)
+        assert out.value is None
