@@ -5,7 +5,8 @@ GPU library is checked against.  Only the test suite, the smoke check and the
 CPU-baseline leg of the benchmark import it.  It shares no code with the GPU
 library and never calls it.
 
-The arithmetic lives in ``gpo.c`` (plain C99, ``double complex``), which
+The arithmetic lives in ``gpo.c`` and, for the circularly, spherically and
+axially symmetric forms, ``gpo_radial.c`` (plain C99, ``double complex``), which
 follows the paper's description of the method (Vudragovic et al., Comput.
 Phys. Commun. 183 (2012) 2021: program summaries (v) and (xiv), "Method of
 solution"; "Summary of revisions" for the routine decomposition calcnu ->
@@ -25,6 +26,7 @@ import numpy as np
 
 _HERE = pathlib.Path(__file__).resolve().parent
 SOURCE = _HERE / "gpo.c"
+SOURCE_RADIAL = _HERE / "gpo_radial.c"
 LIBRARY = _HERE / "libgpo.so"
 
 IMAG = 0
@@ -54,7 +56,7 @@ class OracleError(RuntimeError):
 def build_command() -> list[str]:
     # No -ffast-math and no -march: IEEE semantics, portable to any x86-64 host.
     return ["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared",
-            "-Wall", "-Wextra", "-o", str(LIBRARY), str(SOURCE), "-lm"]
+            "-Wall", "-Wextra", "-o", str(LIBRARY), str(SOURCE), str(SOURCE_RADIAL), "-lm"]
 
 
 def build() -> pathlib.Path:
@@ -89,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.gpo_step_nd.argtypes = [ctypes.c_int] + L.gpo_step.argtypes
         L.gpo_observables_nd.argtypes = [ctypes.c_int] + L.gpo_observables.argtypes
         L.gpo_norm_nd.argtypes = [ctypes.c_int] + L.gpo_norm.argtypes
+        L.gpo_radial_step.argtypes = [ctypes.c_int] + L.gpo_step.argtypes
+        L.gpo_radial_observables.argtypes = [ctypes.c_int] + L.gpo_observables.argtypes
+        L.gpo_radial_step.restype = ctypes.c_int
+        L.gpo_radial_observables.restype = ctypes.c_int
         L.gpo_thomas.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, dp, dp]
         L.gpo_coord.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_int64]
@@ -185,3 +191,27 @@ def coord(n: int, dx: float) -> np.ndarray:
     """The oracle's node coordinates along one axis."""
     L = lib()
     return np.array([L.gpo_coord(int(n), float(dx), i) for i in range(int(n))])
+
+
+GEOMETRIES = {"circular": 1, "spherical": 2, "axial": 3}
+
+
+def radial_step(psi: np.ndarray, geom: str, dx, dt: float, omega, g: float, mode: int,
+                nsteps: int = 1) -> np.ndarray:
+    """Advance a symmetric-trap state in place (gpo_radial.c).  psi has shape
+    (1, 1, N) (circular, spherical: r along the last axis) or (1, Nz, Nrho)
+    (axial); dx = (h_r, dz, unused); omega = (w or gamma, unused, lambda)."""
+    n, d, w = _grid_args(psi, dx, omega)
+    st = lib().gpo_radial_step(GEOMETRIES[geom], n, d, float(dt), w, float(g), int(mode), _ptr(psi), int(nsteps))
+    if st != OK:
+        raise OracleError(st, "radial step")
+    return psi
+
+
+def radial_observables(psi: np.ndarray, geom: str, dx, omega, g: float) -> dict:
+    n, d, w = _grid_args(psi, dx, omega)
+    out = (ctypes.c_double * len(OBS_NAMES))()
+    st = lib().gpo_radial_observables(GEOMETRIES[geom], n, d, w, float(g), _ptr(psi), out)
+    if st != OK:
+        raise OracleError(st, "radial observables")
+    return {k: out[i] for i, k in enumerate(OBS_NAMES)}
