@@ -134,6 +134,32 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
                             gp_mode mode, gp_dtype dtype, void *hip_stream,
                             gp_plan **out);
 
+/* The symmetric traps (the paper's circularly, spherically and axially
+ * symmetric programs, summaries (iv), (ix), (vii) and their real-time
+ * counterparts). */
+typedef enum {
+    GP_GEOM_CIRCULAR = 1,   /* 2D, radial variable r along x; grid (N, 1, 1); trap gamma */
+    GP_GEOM_SPHERICAL = 2,  /* 3D, radial variable r along x; grid (N, 1, 1); trap gamma */
+    GP_GEOM_AXIAL = 3       /* 3D, rho along x and z along y; grid (N_rho, N_z, 1);
+                               trap gamma (rho) and lambda (z) */
+} gp_geom;
+
+/* Plan for a symmetric trap.  Radial nodes sit at r_i = (i + 1/2) dx[0]
+ * (no node at the origin; no flux through it; zero one node past the
+ * last); z nodes (axial) as on a Cartesian axis with spacing dx[1].  The
+ * radial Laplacian is the conservative finite-volume form with face
+ * weights ((i+1) h)^(D-1) and cell weights ((i+1)^D - i^D) h^(D-1) / D
+ * (D = 2 circular and axial, 3 spherical); the cell volume is
+ * S_D h v_i (times dz, axial), S_2 = 2 pi, S_3 = 4 pi, and the norm, the
+ * renormalisation and every observable use it.  nu is unused; lambda only
+ * for the axial trap.  Observables: rms[0], mean[0] for the radial
+ * variable, rms[1], mean[1] for z (axial), rms_r = sqrt(<r^2>) or
+ * sqrt(<rho^2 + z^2>).  Errors as gp_plan_create_nd. */
+gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const double dx[3], double dt,
+                                double gamma, double nu, double lambda, double g,
+                                gp_mode mode, gp_dtype dtype, void *hip_stream,
+                                gp_plan **out);
+
 /* Frees the plan's tables and scratch after waiting for its stream.
  * NULL-safe. */
 gp_status gp_plan_destroy(gp_plan *plan);

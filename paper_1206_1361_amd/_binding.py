@@ -32,7 +32,7 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 
 # Every symbol include/gpssc.h declares.
 EXPORTS = (
-    "gp_plan_create", "gp_plan_create_nd", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
+    "gp_plan_create", "gp_plan_create_nd", "gp_plan_create_radial", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
     "gp_step_schedule", "gp_sync",
     "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(vp)]
     L.gp_plan_create_nd.argtypes = [ctypes.c_int] + L.gp_plan_create.argtypes
     L.gp_plan_create_nd.restype = ctypes.c_int
+    L.gp_plan_create_radial.argtypes = [ctypes.c_int] + L.gp_plan_create.argtypes
+    L.gp_plan_create_radial.restype = ctypes.c_int
     L.gp_plan_destroy.argtypes = [vp]
     L.gp_set_g.argtypes = [vp, dbl]
     L.gp_set_trap.argtypes = [vp, dbl, dbl, dbl]
@@ -282,9 +284,15 @@ class Plan:
     for imaginary time, real torch.float64 ("r64") or torch.float32 ("r32");
     CUDA (HIP) device, contiguous, shape (Nz, Ny, Nx).  ndim = 1 or 2 solves
     the equation in x (and y) only, on a grid with Nz = 1 (and Ny = 1).
+    geometry = "circular" | "spherical" (radial variable along x, grid
+    (N, 1, 1), trap gamma) or "axial" (rho along x, z along y, grid
+    (N_rho, N_z, 1), traps gamma and lam) selects a symmetric trap.
     """
 
-    def __init__(self, grid, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", stream=None, ndim=3):
+    GEOMETRIES = {"circular": 1, "spherical": 2, "axial": 3}
+
+    def __init__(self, grid, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", stream=None, ndim=3,
+                 geometry=None):
         import torch
 
         L = lib()
@@ -300,9 +308,15 @@ class Plan:
         n = (ctypes.c_int64 * 3)(*self.grid)
         d = (ctypes.c_double * 3)(*self.dx)
         self.ndim = int(ndim)
-        _check(L.gp_plan_create_nd(self.ndim, n, d, self.dt, *self.omega, self.g, self.mode, self.dtype,
-                                   self._stream_handle(stream), ctypes.byref(self._handle)),
-               "gp_plan_create_nd")
+        self.geometry = geometry
+        if geometry is not None:
+            _check(L.gp_plan_create_radial(self.GEOMETRIES[geometry], n, d, self.dt, *self.omega, self.g, self.mode,
+                                           self.dtype, self._stream_handle(stream), ctypes.byref(self._handle)),
+                   "gp_plan_create_radial")
+        else:
+            _check(L.gp_plan_create_nd(self.ndim, n, d, self.dt, *self.omega, self.g, self.mode, self.dtype,
+                                       self._stream_handle(stream), ctypes.byref(self._handle)),
+                   "gp_plan_create_nd")
 
     @staticmethod
     def _stream_handle(stream):

@@ -231,6 +231,28 @@ struct SBatchArgs {
     const cx<A> *zt;       // this solve's y or z correction
 };
 
+// Radial Crank-Nicolson (symmetric traps): x holds the grid, coordinates
+// (c0x = -1/2: node i at (i + 1/2) dx), trap, dt and g; tab the per-position
+// coefficients, six arrays of npad entries: rd, rl, ru (right side
+// rd_i u_i + rl_i u_{i-1} + ru_i u_{i+1}), m, a (forward d_i = m_i q_i +
+// a_i d_{i-1}) and b (backward x_i = d_i + b_i x_{i+1}), zero past the line.
+template <typename A>
+struct RadialArgs {
+    XArgs<A> x;
+    const cx<A> *tab;
+    int npad;
+};
+
+// Physical quantities of the symmetric traps: nr radial nodes at
+// (i + 1/2) dr with cell weights v and face weights s (device arrays), nz
+// rows (z nodes of the axial trap at (k - c0z) dz; 1 otherwise).
+struct RadialObsArgs {
+    int nr, nz;
+    double dr, dz, c0z;
+    double hgr, hgz;          // gamma^2/2 (radial), lambda^2/2 (z)
+    const double *v, *s;
+};
+
 // Sums of the observables pass, FP64.
 enum {
     OBS_DENS = 0, OBS_POT, OBS_QUART,
@@ -270,10 +292,22 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, i
                           void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream);
 
-// calcnorm: sums `n` partials in a fixed order, writes 1/sqrt(dv*sum) to
-// *scale and raises *flag if the norm is not finite and positive.
+// calcnorm: sums `n` partials (each times weights[b] when weights is not
+// NULL) in a fixed order, writes 1/sqrt(dv*sum) to *scale and raises *flag
+// if the norm is not finite and positive.
 hipError_t launch_norm_finalize(const double *partials, int n, double dv, double *scale,
-                                int *flag, hipStream_t stream);
+                                int *flag, hipStream_t stream, const double *weights = nullptr);
+
+// calcnu + Crank-Nicolson along a radial axis, one wavefront per line
+// (nlines lines of args.x.nx points).  dens: NULL or |psi|^2 per stored
+// point (one-line states: the norm partials).
+hipError_t launch_nu_r(Prec prec, bool real, int chunk, int nlines, void *psi, const void *args,
+                       const double *scale, double *dens, hipStream_t stream);
+
+// Sums of the symmetric-trap quantities into sums[OBS_NSUMS] (partials:
+// OBS_NSUMS per row of scratch).
+hipError_t launch_radial_observables(Prec prec, const void *psi, const RadialObsArgs &args, double *partials,
+                                     double *sums, hipStream_t stream);
 
 // psi <- psi * (*scale)
 hipError_t launch_scale(Prec prec, void *psi, int64_t elems, const double *scale,

@@ -71,6 +71,14 @@ struct gp_plan {
     gpssc::XArgs<float> xf;
     gpssc::SArgs<double> sd[2];
     gpssc::SArgs<float> sf[2];
+
+    // symmetric traps (gp_plan_create_radial): 0 = Cartesian, else a gp_geom;
+    // x is the radial axis, y the z axis of the axial trap
+    int geom = 0;
+    unsigned char *d_rtab = nullptr;   // six coefficient arrays (arithmetic type)
+    double *d_rv = nullptr, *d_rs = nullptr;   // cell and face weights
+    gpssc::RadialArgs<double> rd;
+    gpssc::RadialArgs<float> rf;
 };
 
 namespace {
@@ -164,7 +172,62 @@ void release(gp_plan *p)
     if (p->d_sums) (void)hipFree(p->d_sums);
     if (p->h_sums) (void)hipHostFree(p->h_sums);
     if (p->h_flag) (void)hipHostFree(p->h_flag);
+    if (p->d_rtab) (void)hipFree(p->d_rtab);
+    if (p->d_rv) (void)hipFree(p->d_rv);
+    if (p->d_rs) (void)hipFree(p->d_rs);
     delete p;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Dimension and solid angle of a symmetric trap's radial axis.
+int radial_dim(int geom) { return geom == GP_GEOM_SPHERICAL ? 3 : 2; }
+double radial_solid_angle(int geom) { return geom == GP_GEOM_SPHERICAL ? 4.0 * kPi : 2.0 * kPi; }
+
+// Volume factor of a grid cell: S_D h (times dz for the axial trap); the
+// cell weights v_i carry the rest.
+double radial_cell(const gp_plan *p)
+{
+    const double c = radial_solid_angle(p->geom) * p->dx[0];
+    return p->geom == GP_GEOM_AXIAL ? c * p->dx[1] : c;
+}
+
+// Radial weights and Crank-Nicolson coefficients, FP64.  Face weights
+// s_i = ((i+1) h)^(D-1) (the face at (i + 1) h), cell weights
+// v_i = ((i+1)^D - i^D) h^(D-1) / D, and with T = -1/2 L,
+// L the finite-volume Laplacian [s_i (u_{i+1} - u_i) - s_{i-1} (u_i - u_{i-1})] / (h^2 v_i)
+// (s_{-1} = 0: no flux through the origin):
+//   right side (1 - tau/2 T) u, left matrix 1 + tau/2 T, the latter
+//   factorised by the Thomas recursion into m_i, a_i (forward) and b_i
+//   (backward).  Positions past the line keep zero coefficients.
+void radial_tables(int dim, int64_t n, double h, double dt, bool real, int npad, std::vector<cplx> &tab,
+                   std::vector<double> &v, std::vector<double> &sf)
+{
+    const cplx tau = real ? cplx(0.0, dt) : cplx(dt, 0.0);
+    v.assign((size_t)n, 0.0);
+    sf.assign((size_t)n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        sf[(size_t)i] = std::pow((double)(i + 1) * h, dim - 1);
+        v[(size_t)i] = (std::pow((double)(i + 1), dim) - std::pow((double)i, dim)) * std::pow(h, dim - 1) / dim;
+    }
+    tab.assign(6 * (size_t)npad, cplx(0.0, 0.0));
+    cplx cprev(0.0, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const double below = i > 0 ? sf[(size_t)i - 1] : 0.0, above = sf[(size_t)i];
+        const double c = 1.0 / (2.0 * h * h * v[(size_t)i]);
+        const cplx t_ii = (below + above) * c, t_lo = -below * c, t_up = -above * c;
+        const cplx half = 0.5 * tau;
+        const cplx l_lo = half * t_lo, l_ii = 1.0 + half * t_ii, l_up = half * t_up;   // left matrix row
+        const cplx den = l_ii - l_lo * cprev;
+        const cplx cur = l_up / den;
+        tab[0 * (size_t)npad + i] = 1.0 - half * t_ii;   // rd
+        tab[1 * (size_t)npad + i] = -half * t_lo;        // rl
+        tab[2 * (size_t)npad + i] = -half * t_up;        // ru
+        tab[3 * (size_t)npad + i] = 1.0 / den;           // m
+        tab[4 * (size_t)npad + i] = -l_lo / den;         // a
+        tab[5 * (size_t)npad + i] = -cur;                // b
+        cprev = cur;
+    }
 }
 
 gp_status check_psi(const gp_plan *p, const void *psi, int64_t elems)
@@ -208,12 +271,20 @@ void set_g(gp_plan *p, double g)
     p->g = g;
     p->xd.g = g;
     p->xf.g = (float)g;
+    p->rd.x.g = g;
+    p->rf.x.g = (float)g;
 }
 
 void set_trap(gp_plan *p, const double om_in[3])
 {
     double om[3];
-    for (int a = 0; a < 3; ++a) om[a] = a < p->ndim ? om_in[a] : 0.0;   // no trap along absent axes
+    if (p->geom) {   // radial axis: gamma; the axial trap's z (stored along y): lambda
+        om[0] = om_in[0];
+        om[1] = p->geom == GP_GEOM_AXIAL ? om_in[2] : 0.0;
+        om[2] = 0.0;
+    } else {
+        for (int a = 0; a < 3; ++a) om[a] = a < p->ndim ? om_in[a] : 0.0;   // no trap along absent axes
+    }
     for (int a = 0; a < 3; ++a) p->omega[a] = om[a];
     p->xd.hgx = 0.5 * om[0] * om[0];
     p->xd.hgy = 0.5 * om[1] * om[1];
@@ -221,6 +292,12 @@ void set_trap(gp_plan *p, const double om_in[3])
     p->xf.hgx = (float)p->xd.hgx;
     p->xf.hgy = (float)p->xd.hgy;
     p->xf.hgz = (float)p->xd.hgz;
+    p->rd.x.hgx = p->xd.hgx;
+    p->rd.x.hgy = p->xd.hgy;
+    p->rd.x.hgz = p->xd.hgz;
+    p->rf.x.hgx = p->xf.hgx;
+    p->rf.x.hgy = p->xf.hgy;
+    p->rf.x.hgz = p->xf.hgz;
 }
 
 // Queues nsteps steps.  With schedules, step s uses g_steps[s] and the trap
@@ -244,14 +321,25 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     for (int a = 0; a < nd; ++a) dv *= p->dx[a];
     // the last sweep leaves the norm partials, one per line along its axis
     double *parts = real ? nullptr : p->d_partials;
-    const int nparts = nd == 3 ? (int)(p->n[0] * p->n[1]) : (nd == 2 ? (int)(p->n[0] * p->n[2])
-                                                                       : (int)(p->n[1] * p->n[2]));
+    int nparts = nd == 3 ? (int)(p->n[0] * p->n[1]) : (nd == 2 ? (int)(p->n[0] * p->n[2])
+                                                                 : (int)(p->n[1] * p->n[2]));
+    const double *weights = nullptr;
+    if (p->geom) {   // symmetric traps: one partial per radial node, weighted by its cell
+        dv = radial_cell(p);
+        nparts = (int)p->n[0];
+        weights = p->d_rv;
+    }
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
         if (g_steps) set_g(p, g_steps[s]);
         if (trap_steps) set_trap(p, trap_steps + 3 * s);
         const double *scale = (!real && s > 0) ? p->d_scale : nullptr;
         e = timed(p, GP_KERNEL_NU_X, [&] {
+            if (p->geom) {
+                const void *rargs = a32 ? (const void *)&p->rf : (const void *)&p->rd;
+                return gpssc::launch_nu_r(prec, real, p->ax[0].chunk, (int)(p->n[1] * p->n[2]), psi, rargs, scale,
+                                          nd == 1 ? parts : nullptr, p->stream);
+            }
             return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
                                       T + p->tab_off[0], scale, nd == 1 ? parts : nullptr, p->stream);
         });
@@ -272,7 +360,8 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         }
         if (e != hipSuccess || real) continue;
         e = timed(p, GP_KERNEL_NORM, [&] {
-            return gpssc::launch_norm_finalize(p->d_partials, nparts, dv, p->d_scale, p->d_flag, p->stream);
+            return gpssc::launch_norm_finalize(p->d_partials, nparts, dv, p->d_scale, p->d_flag, p->stream,
+                                               weights);
         });
     }
     if (e == hipSuccess && !real) {
@@ -282,6 +371,62 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     }
     if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
     p->steps_done += nsteps;
+    return GP_OK;
+}
+
+// calcmuen / calcrms of a symmetric trap from the weighted sums of the
+// radial observables kernel: dV = S_D h (dz) times the cell weights; the
+// radial kinetic term summed by parts over the faces, S_D (dz) / (2h) sum
+// s_i |u_{i+1} - u_i|^2; the z links of the axial trap as in Cartesian
+// space.  rms and mean: slot 0 the radial variable, slot 1 z (axial).
+gp_status radial_observables(gp_plan *p, const void *psi, gp_obs *out, gp_status earlier)
+{
+    gpssc::RadialObsArgs a;
+    a.nr = (int)p->n[0];
+    a.nz = (int)p->n[1];
+    a.dr = p->dx[0];
+    a.dz = p->geom == GP_GEOM_AXIAL ? p->dx[1] : 1.0;
+    a.c0z = 0.5 * (double)(p->n[1] - 1);
+    a.hgr = 0.5 * p->omega[0] * p->omega[0];
+    a.hgz = 0.5 * p->omega[1] * p->omega[1];
+    a.v = p->d_rv;
+    a.s = p->d_rs;
+    hipError_t e = timed(p, GP_KERNEL_OBS, [&] {
+        return gpssc::launch_radial_observables(static_cast<gpssc::Prec>(p->dtype), psi, a, p->d_obs_partials,
+                                                p->d_sums, p->stream);
+    });
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_sums, p->d_sums, sizeof(double) * gpssc::OBS_NSUMS, hipMemcpyDeviceToHost,
+                           p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return fail_hip(e, "computing observables");
+    const double *S = p->h_sums;
+    const double dv = radial_cell(p);
+    const double hz = a.dz;
+    const double norm = dv * S[gpssc::OBS_DENS];
+    double kin = radial_solid_angle(p->geom) * (p->geom == GP_GEOM_AXIAL ? hz : 1.0) / (2.0 * p->dx[0]) *
+                 S[gpssc::OBS_LINKX];
+    if (p->geom == GP_GEOM_AXIAL) kin += 0.5 * dv * S[gpssc::OBS_LINKY] / (hz * hz);
+    out->norm = norm;
+    out->kinetic = kin / norm;
+    out->potential = dv * S[gpssc::OBS_POT] / norm;
+    out->interaction = p->g * dv * S[gpssc::OBS_QUART] / (norm * norm);
+    out->energy = out->kinetic + out->potential + 0.5 * out->interaction;
+    out->mu = out->kinetic + out->potential + out->interaction;
+    out->rms[0] = std::sqrt(dv * S[gpssc::OBS_M2X] / norm);
+    out->mean[0] = dv * S[gpssc::OBS_M1X] / norm;
+    out->rms[1] = p->geom == GP_GEOM_AXIAL ? std::sqrt(dv * S[gpssc::OBS_M2Y] / norm) : 0.0;
+    out->mean[1] = p->geom == GP_GEOM_AXIAL ? dv * S[gpssc::OBS_M1Y] / norm : 0.0;
+    out->rms[2] = 0.0;
+    out->mean[2] = 0.0;
+    out->rms_r = std::sqrt(dv * (S[gpssc::OBS_M2X] + S[gpssc::OBS_M2Y]) / norm);
+    out->steps_done = p->steps_done;
+    if (earlier != GP_OK) return earlier;
+    const double all[] = {out->norm, out->mu, out->energy, out->rms[0], out->rms[1], out->rms_r, out->mean[0],
+                          out->mean[1], out->kinetic, out->potential, out->interaction};
+    bool ok = norm > 0.0;
+    for (double v : all) ok = ok && std::isfinite(v);
+    if (!ok) return fail(GP_ERR_NONFINITE, "psi has a zero or non-finite norm or observable");
     return GP_OK;
 }
 
@@ -454,6 +599,72 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
     return GP_OK;
 }
 
+gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const double dx[3], double dt,
+                                double gamma, double nu, double lambda, double g, gp_mode mode, gp_dtype dtype,
+                                void *hip_stream, gp_plan **out)
+{
+    if (!out) return fail(GP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (geom != GP_GEOM_CIRCULAR && geom != GP_GEOM_SPHERICAL && geom != GP_GEOM_AXIAL)
+        return fail(GP_ERR_INVALID, "unknown geometry");
+    if (!std::isfinite(nu) || nu < 0.0 || !std::isfinite(lambda) || lambda < 0.0)
+        return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+    const int nd = geom == GP_GEOM_AXIAL ? 2 : 1;
+    // gamma along the radial axis (x), lambda along z (stored along y) for the axial trap
+    gp_status st = gp_plan_create_nd(nd, grid, dx, dt, gamma, geom == GP_GEOM_AXIAL ? lambda : 0.0, 0.0, g, mode,
+                                     dtype, hip_stream, out);
+    if (st != GP_OK) return st;
+    gp_plan *p = *out;
+    *out = nullptr;
+    p->geom = geom;
+    const int chunk = p->ax[0].chunk;
+    const int npad = gpssc::kWave * chunk;
+    std::vector<cplx> tab;
+    std::vector<double> v, sf;
+    radial_tables(radial_dim(geom), grid[0], dx[0], dt, mode == GP_MODE_REAL, npad, tab, v, sf);
+    std::vector<unsigned char> bytes;
+    if (arith_f32(dtype)) {
+        std::vector<cx<float>> t(tab.size());
+        for (size_t i = 0; i < tab.size(); ++i) t[i] = to_cx<float>(tab[i]);
+        bytes.assign(reinterpret_cast<unsigned char *>(t.data()), reinterpret_cast<unsigned char *>(t.data() + t.size()));
+    } else {
+        std::vector<cx<double>> t(tab.size());
+        for (size_t i = 0; i < tab.size(); ++i) t[i] = to_cx<double>(tab[i]);
+        bytes.assign(reinterpret_cast<unsigned char *>(t.data()), reinterpret_cast<unsigned char *>(t.data() + t.size()));
+    }
+    DeviceGuard guard(p->device);
+    hipError_t e = hipMalloc((void **)&p->d_rtab, bytes.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_rv, sizeof(double) * v.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_rs, sizeof(double) * sf.size());
+    // the observables kernel keeps one partial row per z node
+    if (e == hipSuccess && p->n_obs_blocks < (int)grid[1]) {
+        (void)hipFree(p->d_obs_partials);
+        p->d_obs_partials = nullptr;
+        e = hipMalloc((void **)&p->d_obs_partials, sizeof(double) * gpssc::OBS_NSUMS * (size_t)grid[1]);
+        p->n_obs_blocks = (int)grid[1];
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_rtab, bytes.data(), bytes.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_rv, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_rs, sf.data(), sizeof(double) * sf.size(), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release(p);
+        return e == hipErrorOutOfMemory ? fail(GP_ERR_NOMEM, "hipMalloc failed") : fail_hip(e, "radial tables");
+    }
+    p->rd.x = p->xd;
+    p->rf.x = p->xf;
+    p->rd.x.c0x = -0.5;    // node i at (i + 1/2) h
+    p->rf.x.c0x = -0.5f;
+    p->rd.tab = reinterpret_cast<const cx<double> *>(p->d_rtab);
+    p->rf.tab = reinterpret_cast<const cx<float> *>(p->d_rtab);
+    p->rd.npad = p->rf.npad = npad;
+    *out = p;
+    return GP_OK;
+}
+
 gp_status gp_plan_destroy(gp_plan *plan)
 {
     if (!plan) return GP_OK;
@@ -529,6 +740,7 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
     const gp_status earlier = read_flag(p);
     if (earlier == GP_ERR_DEVICE) return earlier;
 
+    if (p->geom) return radial_observables(p, psi, out, earlier);
     gpssc::ObsArgs<double> a;
     a.nx = (int)p->n[0];
     a.ny = (int)p->n[1];
@@ -600,12 +812,13 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
         nzc[a] = a32 ? kf[a]->nzc : kd[a]->nzc;
     }
     const char *names[] = {"c128", "c64", "c64/f64", "r64", "r32"};
+    const char *geoms[] = {"", " circular", " spherical", " axial"};
     const char *dt = names[(int)p->dtype];
     std::snprintf(buf, len,
-                  "grid %lldx%lldx%lld %dD %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
+                  "grid %lldx%lldx%lld %dD%s %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
                   "%d blocks | y: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks | "
                   "z: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks",
-                  (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->ndim,
+                  (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->ndim, geoms[p->geom],
                   p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
                   p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->y_blocks,
                   p->ax[2].chunk, p->ax[2].lanes, p->xt_z, nst[2], nzc[2], p->z_blocks);

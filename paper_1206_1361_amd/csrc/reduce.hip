@@ -30,11 +30,19 @@ __device__ double block_sum(double v, double *red)
 
 __global__ void __launch_bounds__(kReduceThreads)
 calcnorm_finalize_kernel(const double *__restrict__ partials, int n, double dv,
-                         double *__restrict__ scale, int *__restrict__ flag)
+                         double *__restrict__ scale, int *__restrict__ flag,
+                         const double *__restrict__ weights)
 {
     __shared__ double red[kReduceThreads];
     double acc = 0.0;
-    for (int b = threadIdx.x; b < n; b += kReduceThreads) acc += partials[b];
+    if (weights) {
+        for (int b = threadIdx.x; b < n; b += kReduceThreads) {
+#pragma clang fp contract(off)
+            acc += weights[b] * partials[b];
+        }
+    } else {
+        for (int b = threadIdx.x; b < n; b += kReduceThreads) acc += partials[b];
+    }
     const double sum = block_sum(acc, red);
     if (threadIdx.x == 0) {
         const double norm = dv * sum;
@@ -294,10 +302,10 @@ hipError_t launch_observables_batch(Prec prec, int nact, const int *active, void
 }
 
 hipError_t launch_norm_finalize(const double *partials, int n, double dv, double *scale,
-                                int *flag, hipStream_t stream)
+                                int *flag, hipStream_t stream, const double *weights)
 {
     hipLaunchKernelGGL(calcnorm_finalize_kernel, dim3(1), dim3(kReduceThreads), 0, stream,
-                       partials, n, dv, scale, flag);
+                       partials, n, dv, scale, flag, weights);
     return hipGetLastError();
 }
 

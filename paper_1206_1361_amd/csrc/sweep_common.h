@@ -169,4 +169,37 @@ __device__ __forceinline__ cx<A> nu_factor(cx<A> v, A phi)
     return cx<A>{v.re * f, v.im * f};
 }
 
+// ---- one x line per wavefront: lane l holds the chunk [l*C, l*C + C) ----
+
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_up_c(cx<A> v, int d)
+{
+    return cx<A>{__shfl_up(v.re, d, kWave), __shfl_up(v.im, d, kWave)};
+}
+
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d)
+{
+    return cx<A>{__shfl_down(v.re, d, kWave), __shfl_down(v.im, d, kWave)};
+}
+
+// LDS slot of line element e: one padding slot after every C elements keeps
+// the chunk-order reads (stride C+1 elements between lanes) off one bank.
+template <int C>
+__device__ __forceinline__ int xslot(int e) { return e + e / C; }
+
+template <typename S, int C>
+__device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row, int nx)
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+        const int e = r * kWave + lane;
+        v[r] = szero<S>();
+        if (e < nx) v[r] = stream_load(row + e);
+    }
+}
+
+// One wavefront per block; block b solves lines b, b + G, ... (G =
+// gridDim.x).  The plan launches one block per line.
 }  // namespace gpssc

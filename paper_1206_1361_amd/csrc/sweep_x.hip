@@ -22,23 +22,6 @@
 
 namespace gpssc {
 
-template <typename A>
-__device__ __forceinline__ cx<A> shfl_up_c(cx<A> v, int d)
-{
-    return cx<A>{__shfl_up(v.re, d, kWave), __shfl_up(v.im, d, kWave)};
-}
-
-template <typename A>
-__device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d)
-{
-    return cx<A>{__shfl_down(v.re, d, kWave), __shfl_down(v.im, d, kWave)};
-}
-
-// LDS slot of line element e: one padding slot after every C elements keeps
-// the chunk-order reads (stride C+1 elements between lanes) off one bank.
-template <int C>
-__device__ __forceinline__ int xslot(int e) { return e + e / C; }
-
 // One x line: psi values in row order (element r*64 + lane) -> solved line,
 // in row order, written back through the same LDS buffer.
 template <typename S, typename A, int C, bool REAL>
@@ -117,20 +100,6 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
     for (int r = 0; r < C; ++r) row_vals[r] = buf[xslot<C>(r * kWave + lane)];
 }
 
-template <typename S, int C>
-__device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row, int nx)
-{
-    const int lane = threadIdx.x;
-#pragma unroll
-    for (int r = 0; r < C; ++r) {
-        const int e = r * kWave + lane;
-        v[r] = szero<S>();
-        if (e < nx) v[r] = stream_load(row + e);
-    }
-}
-
-// One wavefront per block; block b solves lines b, b + G, ... (G =
-// gridDim.x).  The plan launches one block per line.
 // partials: NULL, or one double per line receiving sum |psi|^2 of the stored
 // line (the norm partials of imaginary time when x is the only variable),
 // summed per lane in row order, then over the lanes by a fixed tree.

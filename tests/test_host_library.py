@@ -286,3 +286,15 @@ def test_plan_create_nd_rejects_bad_shapes_before_any_device_call():
         assert L.gp_plan_create_nd(ndim, n, d, 0.01, 1.0, 1.0, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == \
             _binding.ERR_INVALID, (ndim, grid)
         assert out.value is None
+
+
+def test_plan_create_radial_rejects_bad_arguments_before_any_device_call():
+    L = gp.lib()
+    d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    for geom, grid, nu in ((0, (8, 1, 1), 1.0), (4, (8, 1, 1), 1.0), (1, (8, 2, 1), 1.0), (3, (8, 8, 2), 1.0),
+                           (2, (8, 1, 1), float("nan"))):
+        n = (ctypes.c_int64 * 3)(*grid)
+        out = ctypes.c_void_p(5)
+        assert L.gp_plan_create_radial(geom, n, d, 0.01, 1.0, nu, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == \
+            _binding.ERR_INVALID, (geom, grid)
+        assert out.value is None
