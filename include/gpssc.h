@@ -219,6 +219,15 @@ gp_status gp_observables(gp_plan *plan, const void *psi_dev, int64_t psi_elems,
  * scratch), excluding psi.  Returns 0 for an invalid grid. */
 size_t gp_plan_footprint_bytes(const int64_t grid[3], gp_dtype dtype);
 
+/* Density profiles of psi (the paper's programs write the density along the
+ * axes as output): px[i] = dy dz sum_{j,k} |psi_ijk|^2, and likewise py[Ny],
+ * pz[Nz], with the spacings of the present axes only (gp_plan_create_nd).
+ * Host arrays of Nx, Ny, Nz doubles; FP64 sums in a fixed order; waits for
+ * the result.  Allocates a small device buffer per call.  Cartesian plans
+ * only (GP_ERR_UNSUPPORTED for the symmetric traps). */
+gp_status gp_density_profiles(gp_plan *plan, const void *psi_dev, int64_t psi_elems, double *px, double *py,
+                              double *pz);
+
 /* Writes a one-line description of the plan's launch shapes into buf
  * (NUL-terminated, truncated to len). */
 gp_status gp_plan_describe(const gp_plan *plan, char *buf, size_t len);

@@ -34,7 +34,7 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 EXPORTS = (
     "gp_plan_create", "gp_plan_create_nd", "gp_plan_create_radial", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
     "gp_step_schedule", "gp_sync",
-    "gp_observables", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
+    "gp_observables", "gp_density_profiles", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
     "gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active", "gp_batch_step",
     "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe",
@@ -143,6 +143,8 @@ def lib() -> ctypes.CDLL:
     L.gp_step.argtypes = [vp, vp, i64, i64]
     L.gp_sync.argtypes = [vp]
     L.gp_observables.argtypes = [vp, vp, i64, ctypes.POINTER(GPObs)]
+    L.gp_density_profiles.argtypes = [vp, vp, i64, dp, dp, dp]
+    L.gp_density_profiles.restype = ctypes.c_int
     L.gp_plan_footprint_bytes.argtypes = [i64p, ctypes.c_int]
     L.gp_plan_footprint_bytes.restype = sz
     L.gp_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
@@ -370,6 +372,18 @@ class Plan:
     def set_trap(self, gamma: float, nu: float, lam: float) -> None:
         _check(lib().gp_set_trap(self._handle, float(gamma), float(nu), float(lam)), "gp_set_trap")
         self.omega = (float(gamma), float(nu), float(lam))
+
+    def density_profiles(self, psi):
+        """(px, py, pz): |psi|^2 integrated over the other two axes."""
+        import numpy as np
+
+        ptr, n = self._psi(psi)
+        self._use_current_stream()
+        out = [np.zeros(v) for v in self.grid]
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().gp_density_profiles(self._handle, ptr, n, *[o.ctypes.data_as(dp) for o in out]),
+               "gp_density_profiles")
+        return tuple(out)
 
     def step_schedule(self, psi, g_steps=None, trap_steps=None):
         """Queue one step per entry of g_steps (and/or rows of trap_steps,

@@ -304,6 +304,11 @@ hipError_t launch_norm_finalize(const double *partials, int n, double dv, double
 hipError_t launch_nu_r(Prec prec, bool real, int chunk, int nlines, void *psi, const void *args,
                        const double *scale, double *dens, hipStream_t stream);
 
+// Density profiles into out[nx + ny + nz]: per node of x, then y, then z,
+// the sum of |psi|^2 over the other two axes times w[axis].
+hipError_t launch_profiles(Prec prec, const void *psi, int nx, int ny, int nz, const double w[3], double *out,
+                           hipStream_t stream);
+
 // Sums of the symmetric-trap quantities into sums[OBS_NSUMS] (partials:
 // OBS_NSUMS per row of scratch).
 hipError_t launch_radial_observables(Prec prec, const void *psi, const RadialObsArgs &args, double *partials,

@@ -800,6 +800,41 @@ gp_status gp_observables(gp_plan *p, const void *psi, int64_t psi_elems, gp_obs 
     return GP_OK;
 }
 
+gp_status gp_density_profiles(gp_plan *p, const void *psi, int64_t psi_elems, double *px, double *py, double *pz)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (!px || !py || !pz) return fail(GP_ERR_INVALID, "px, py and pz are required");
+    if (p->geom) return fail(GP_ERR_UNSUPPORTED, "density profiles are for Cartesian plans");
+    DeviceGuard guard(p->device);
+    gp_status st = check_psi(p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    const int64_t total = p->n[0] + p->n[1] + p->n[2];
+    // profile weights: the spacings of the other present axes
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        w[a] = 1.0;
+        for (int b = 0; b < p->ndim; ++b)
+            if (b != a) w[a] *= p->dx[b];
+    }
+    double *d = nullptr, *h = nullptr;
+    hipError_t e = hipMalloc((void **)&d, sizeof(double) * (size_t)total);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h, sizeof(double) * (size_t)total, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = gpssc::launch_profiles(static_cast<gpssc::Prec>(p->dtype), psi, (int)p->n[0], (int)p->n[1], (int)p->n[2],
+                                   w, d, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(double) * (size_t)total, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) {
+        std::memcpy(px, h, sizeof(double) * (size_t)p->n[0]);
+        std::memcpy(py, h + p->n[0], sizeof(double) * (size_t)p->n[1]);
+        std::memcpy(pz, h + p->n[0] + p->n[1], sizeof(double) * (size_t)p->n[2]);
+    }
+    if (d) (void)hipFree(d);
+    if (h) (void)hipHostFree(h);
+    if (e != hipSuccess) return fail_hip(e, "computing density profiles");
+    return GP_OK;
+}
+
 gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
 {
     if (!p || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_plan_describe arguments");

@@ -347,3 +347,54 @@ hipError_t launch_observables(Prec prec, const void *psi, const ObsArgs<double> 
 }
 
 }  // namespace gpssc
+
+namespace gpssc {
+
+// Density profiles: the density integrated over the other two axes, per
+// node of each axis.  One block per node of the profiled axis; its threads
+// stride over the other two in a fixed order, then a fixed tree.
+template <typename S>
+__global__ void __launch_bounds__(kReduceThreads)
+profile_kernel(const S *__restrict__ psi, int nx, int ny, int nz, int axis, double w, double *__restrict__ out)
+{
+    __shared__ double red[kReduceThreads];
+    const int node = blockIdx.x;
+    const int64_t m = axis == 0 ? (int64_t)ny * nz : (axis == 1 ? (int64_t)nx * nz : (int64_t)nx * ny);
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < m; q += kReduceThreads) {
+#pragma clang fp contract(off)
+        int64_t p;
+        if (axis == 0) {
+            p = q * nx + node;                               // q = k*ny + j
+        } else if (axis == 1) {
+            const int64_t k = q / nx, i = q - k * nx;
+            p = (k * ny + node) * nx + i;
+        } else {
+            p = (int64_t)node * nx * ny + q;                 // q = j*nx + i
+        }
+        const S v = psi[p];
+        acc += sre(v) * sre(v) + sim(v) * sim(v);
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[node] = w * s;
+}
+
+hipError_t launch_profiles(Prec prec, const void *psi, int nx, int ny, int nz, const double w[3], double *out,
+                           hipStream_t stream)
+{
+    const int n[3] = {nx, ny, nz};
+    double *dst = out;
+    for (int axis = 0; axis < 3; ++axis) {
+        hipError_t e = with_storage(prec, [&](auto tag) {
+            using S = decltype(tag);
+            hipLaunchKernelGGL(profile_kernel<S>, dim3((unsigned)n[axis]), dim3(kReduceThreads), 0, stream,
+                               static_cast<const S *>(psi), nx, ny, nz, axis, w[axis], dst);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+        dst += n[axis];
+    }
+    return hipSuccess;
+}
+
+}  // namespace gpssc

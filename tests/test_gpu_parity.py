@@ -287,3 +287,28 @@ def test_modulated_g_and_trap_schedule_matches_oracle(mode, dtype):
     tpsi, _ = TOL[dtype]
     assert rel(to_host(psi), ref) <= tpsi
     assert abs(gobs["mu"] - robs["mu"]) <= TOL_OBS_SMALL[dtype] * abs(robs["mu"])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "r64"])
+@pytest.mark.parametrize("ndim,grid", [(3, (33, 20, 17)), (2, (40, 24, 1)), (1, (70, 1, 1))])
+def test_density_profiles(dtype, ndim, grid):
+    """Integrated densities along each axis from the oracle-propagated state:
+    their sums give the norm, and each equals the brute-force marginal."""
+    dx = (0.3, 0.25, 0.2)
+    psi = inputs.smooth_random_state(grid, dx, (1.0, 1.2, 1.5), seed=4)
+    if dtype == "r64":
+        psi = psi.real.astype(np.complex128)
+    oracle.step(psi, dx, 0.01, (1.0, 1.2, 1.5), 20.0, oracle.IMAG, 3, ndim=ndim)
+    t = torch.from_numpy(psi.real.copy() if dtype == "r64" else psi).to(
+        {"c128": torch.complex128, "c64": torch.complex64, "r64": torch.float64}[dtype]).cuda()
+    dens = np.abs(t.cpu().numpy().astype(np.complex128)) ** 2       # the stored values
+    with gp.Plan(grid, dx, 0.01, 1.0, 1.2, 1.5, 20.0, mode="imag", dtype=dtype, ndim=ndim) as p:
+        px, py, pz = p.density_profiles(t)
+        norm = p.observables(t)["norm"]
+    w = [np.prod([dx[b] for b in range(ndim) if b != a]) for a in range(3)]
+    ref = [dens.sum(axis=(0, 1)) * w[0], dens.sum(axis=(0, 2)) * w[1], dens.sum(axis=(1, 2)) * w[2]]
+    for got, want in zip((px, py, pz), ref):
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(want)
+    for a, prof in enumerate((px, py, pz)):
+        d = dx[a] if a < ndim else 1.0
+        assert abs(prof.sum() * d - norm) <= 1e-12 * norm
