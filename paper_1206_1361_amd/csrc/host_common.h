@@ -50,12 +50,17 @@ inline size_t storage_bytes(gp_dtype d)
 }
 
 // Most chunks per y/z line.  FP32 arithmetic affords 16-point chunks, so 32
-// chunks cover 512 points; real FP64 storage takes 32 chunks of at most 8
-// points on lines up to 256 (so blocks can hold 32 columns: 256-byte rows),
-// 64 chunks beyond; complex FP64 keeps 64 chunks of at most 8 points.
+// chunks cover 512 points.  FP64 keeps chunks of at most 8 points (about 73
+// registers, so two blocks of up to 768 threads share a compute unit) while
+// that needs at most 48 chunks; longer lines would need blocks too large
+// for two to fit, so they take 16-point chunks at 32 chunks per line, which
+// lets a block hold twice the columns (wider rows per load) at the same
+// occupancy.  Real FP64 storage also takes 32 chunks of 8 points on lines
+// up to 256, so its blocks hold 32 columns (256-byte rows).
 inline int max_lanes_for(gp_dtype dtype, int64_t n)
 {
     if (arith_f32(dtype)) return 32;
+    if (n > 8 * 48) return 32;
     if (dtype == GP_R64 && n <= 8 * 32) return 32;
     return gpssc::kMaxLanesYZ;
 }
