@@ -100,12 +100,6 @@ __device__ __forceinline__ void chunk_correct(cx<A> (&u)[C], cx<A> y0, const cx<
         if (pos0 + c < nzc) u[c] = kfma<REAL>(zt[pos0 + c], y0, u[c]);
 }
 
-// The library sin/cos for phases beyond pi/4, kept out of line: the path is
-// rare (a phase that large per step means a very coarse time step), and
-// inlining it would raise the register count of the whole sweep.
-template <typename A> __device__ __attribute__((noinline)) void sincos_lib(A x, A *s, A *c);
-template <> __device__ __attribute__((noinline)) void sincos_lib<double>(double x, double *s, double *c) { sincos(x, s, c); }
-template <> __device__ __attribute__((noinline)) void sincos_lib<float>(float x, float *s, float *c) { sincosf(x, s, c); }
 template <typename A> __device__ __forceinline__ A exp_lib(A x);
 template <> __device__ __forceinline__ double exp_lib<double>(double x) { return exp(x); }
 template <> __device__ __forceinline__ float exp_lib<float>(float x) { return expf(x); }
@@ -152,17 +146,54 @@ __device__ __forceinline__ void sincos_taylor(float x, float *s, float *c)
     *c = fmaf(-z, pc, 1.0f);
 }
 
+// sin and cos of any phase: Cody-Waite reduction x = k pi/2 + r,
+// |r| <= pi/4, with pi/2 split into three parts (each the correctly rounded
+// remainder of pi/2 after the previous ones) applied by fused multiply-adds,
+// then the Taylor polynomials on r and the rotation by the quadrant k mod 4.
+// The remainder keeps a few ulps for |x| up to about 1e5 (FP64) or 1e3
+// (FP32), far beyond any meaningful phase per step.  It is written inline:
+// a library call here would make the sweep reserve registers for the call.
+template <typename A> struct half_pi;
+template <> struct half_pi<double> {
+    static constexpr double inv = 0.6366197723675814;             // 2/pi
+    static constexpr double p1 = 0x1.921fb54442d18p+0;
+    static constexpr double p2 = 0x1.1a62633145c07p-54;
+    static constexpr double p3 = -0x1.f1976b7ed8fbcp-110;
+};
+template <> struct half_pi<float> {
+    static constexpr float inv = 0.63661975f;
+    static constexpr float p1 = 1.5707963705062866f;
+    static constexpr float p2 = -4.371138828673793e-08f;
+    static constexpr float p3 = -1.7151245100058819e-15f;
+};
+
+template <typename A>
+__device__ __forceinline__ void sincos_reduced(A x, A *s, A *c)
+{
+    using H = half_pi<A>;
+    const A k = rint(x * H::inv);
+    const A r = fma(-k, H::p3, fma(-k, H::p2, fma(-k, H::p1, x)));
+    A sr, cr;
+    sincos_taylor(r, &sr, &cr);
+    const int q = (int)((long long)k & 3);
+    A ss = (q & 1) ? cr : sr;
+    A cc = (q & 1) ? sr : cr;
+    if (q & 2) ss = -ss;
+    if ((q + 1) & 2) cc = -cc;
+    *s = ss;
+    *c = cc;
+}
+
 // calcnu phase factor: v * exp(-i phi) (real time) or v * exp(-phi)
 // (imaginary time), phi = dt * (V + g|v|^2).
 template <bool REAL, typename A>
 __device__ __forceinline__ cx<A> nu_factor(cx<A> v, A phi)
 {
     if (REAL) {
+        // one path for every phase: for |phi| < pi/4 the reduction leaves
+        // k = 0 and r = phi exactly
         A sn, cs;
-        if (fabs(phi) <= (A)0.78539816339744830962)
-            sincos_taylor(phi, &sn, &cs);
-        else
-            sincos_lib<A>(phi, &sn, &cs);
+        sincos_reduced(phi, &sn, &cs);
         return cx<A>{fma(v.re, cs, v.im * sn), fma(v.im, cs, -v.re * sn)};
     }
     const A f = exp_lib<A>(-phi);

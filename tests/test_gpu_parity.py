@@ -312,3 +312,25 @@ def test_density_profiles(dtype, ndim, grid):
     for a, prof in enumerate((px, py, pz)):
         d = dx[a] if a < ndim else 1.0
         assert abs(prof.sum() * d - norm) <= 1e-12 * norm
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_large_phases_match_oracle(dtype):
+    """Real time with a coarse step: dt V reaches ~17, so the phase factor
+    goes through the pi/2 reduction in every quadrant.  g is small: with
+    dt g |psi|^2 of order 1 or more, rounding differences in |psi|^2 grow
+    by that factor every step (in any implementation), and the comparison
+    would measure that growth instead of the kernel."""
+    grid, dx, dt = (24, 20, 16), (0.3, 0.3, 0.3), 0.3
+    omega, g = (3.0, 2.5, 2.0), 2.0
+    psi0 = inputs.smooth_random_state(grid, dx, omega, seed=21)
+    x, y, z = inputs.mesh(grid, dx)
+    vmax = float(np.max(0.5 * (omega[0] ** 2 * x ** 2 + omega[1] ** 2 * y ** 2 + omega[2] ** 2 * z ** 2)))
+    assert dt * vmax > 15.0
+    ref = psi0.copy()
+    oracle.step(ref, dx, dt, omega, g, oracle.REAL, 3)
+    t = to_dev(psi0, dtype)
+    with gp.Plan(grid, dx, dt, *omega, g, mode="real", dtype=dtype) as p:
+        p.step(t, 3)
+    got = t.cpu().numpy().astype(np.complex128)
+    assert rel(got, ref) <= (1e-12 if dtype == "c128" else 2e-5)
