@@ -101,10 +101,15 @@ inline bool sweep_shape(int64_t n, int axis, int *chunk, int *lanes, int max_lan
 #define GPSSC_YZ_COLS 64
 #endif
 
-inline int strided_columns(int64_t nx, int lanes)
+// FP64 arithmetic with 16-point chunks needs about 114 registers, so a
+// compute unit holds 16 of its waves: blocks of at most 512 threads let two
+// of them share it (measured faster than one block of 1024 with twice the
+// row width).
+inline int strided_columns(int64_t nx, int lanes, int chunk, gp_dtype dtype)
 {
+    const int max_threads = (!arith_f32(dtype) && chunk >= 16) ? gpssc::kMaxBlockYZ / 2 : gpssc::kMaxBlockYZ;
     int xt = GPSSC_YZ_COLS;
-    while (xt * lanes > gpssc::kMaxBlockYZ) xt /= 2;
+    while (xt > 1 && xt * lanes > max_threads) xt /= 2;
     while (xt > 16 && xt / 2 >= nx) xt /= 2;
     return xt;
 }

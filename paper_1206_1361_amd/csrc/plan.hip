@@ -147,8 +147,8 @@ size_t footprint(const int64_t grid[3], gp_dtype dtype, int *xt_y, int *xt_z)
     size_t tab = 0;
     for (int a = 0; a < 3; ++a) tab += (size_t)c[a] * l[a];
     tab *= cs;
-    const int xy = strided_columns(grid[0], l[1]);
-    const int xz = strided_columns(grid[0], l[2]);
+    const int xy = strided_columns(grid[0], l[1], c[1], dtype);
+    const int xz = strided_columns(grid[0], l[2], c[2], dtype);
     if (xt_y) *xt_y = xy;
     if (xt_z) *xt_z = xz;
     const size_t zblocks = (size_t)grid[0] * (size_t)grid[1];   // norm partials, one per z line

@@ -51,8 +51,8 @@ inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
         c.grid[a] = grid[a];
         sweep_shape(grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype, grid[a]));
     }
-    c.xt_y = strided_columns(c.grid[0], c.lanes[1]);
-    c.xt_z = strided_columns(c.grid[0], c.lanes[2]);
+    c.xt_y = strided_columns(c.grid[0], c.lanes[1], c.chunk[1], dtype);
+    c.xt_z = strided_columns(c.grid[0], c.lanes[2], c.chunk[2], dtype);
     class_tiles(c);
     return c;
 }
