@@ -361,6 +361,8 @@ def main() -> int:
         from paper_1206_1361_amd import serve
 
         out["serve"] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype="c64", verify=4, log=log)
+        out["serve_real_ground_states"] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype="c64", verify=4,
+                                                    real_states=True, log=log)
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(w, psi_host, args.cpu_seconds)

@@ -343,11 +343,15 @@ typedef struct {
     gp_mode mode;
     int64_t steps;        /* real time: steps to run; imaginary time: the step cap; >= 1 */
     double tol;           /* imaginary time: |delta mu| stopping tolerance (0: run to the cap) */
-    const void *psi_in;   /* host memory: the initial state, Nx*Ny*Nz elements of the server's dtype,
-                             in gp_step's layout; read at admission */
+    const void *psi_in;   /* host memory: the initial state, Nx*Ny*Nz elements of the server's dtype
+                             (or of its real counterpart, see real_state), in gp_step's layout;
+                             read at admission */
     void *psi_out;        /* host memory for the final state (may be psi_in); written before the
                              result is reported */
     uint64_t tag;         /* the caller's, returned in the result */
+    int real_state;       /* imaginary time only: psi_in and psi_out hold real values (double on a
+                             GP_C128 server, float on a GP_C64 one) and the solve runs on real
+                             storage (GP_R64 / GP_R32: half the bytes, the same arithmetic) */
 } gp_request;
 
 typedef struct {
@@ -365,6 +369,9 @@ typedef struct {
     int64_t graph_captures;
     int64_t solve_steps;     /* steps summed over solves */
     uint64_t bytes_in_use, bytes_peak, bytes_budget;
+    double seconds_copy_in, seconds_copy_out, seconds_rounds;   /* engine time: admissions' copies in,
+                                                                    finished states out, queued rounds
+                                                                    up to their completion */
 } gp_server_counters;
 
 /* Device bytes one request of this grid, dtype and mode holds while resident

@@ -90,7 +90,7 @@ class GPRequest(ctypes.Structure):
         ("grid", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3), ("dt", ctypes.c_double),
         ("trap", ctypes.c_double * 3), ("g", ctypes.c_double), ("mode", ctypes.c_int),
         ("steps", ctypes.c_int64), ("tol", ctypes.c_double), ("psi_in", ctypes.c_void_p),
-        ("psi_out", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+        ("psi_out", ctypes.c_void_p), ("tag", ctypes.c_uint64), ("real_state", ctypes.c_int),
     ]
 
 
@@ -105,7 +105,8 @@ class GPResult(ctypes.Structure):
 class GPServerCounters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "queued", "resident", "max_resident",
                                                 "quanta", "graph_captures", "solve_steps")] + \
-               [(n, ctypes.c_uint64) for n in ("bytes_in_use", "bytes_peak", "bytes_budget")]
+               [(n, ctypes.c_uint64) for n in ("bytes_in_use", "bytes_peak", "bytes_budget")] + \
+               [(n, ctypes.c_double) for n in ("seconds_copy_in", "seconds_copy_out", "seconds_rounds")]
 
 
 _lib = None
@@ -583,11 +584,16 @@ class Server:
 
     def submit(self, psi_in, *, dx, dt, trap, g, mode="imag", steps, tol=0.0, psi_out=None, tag=0) -> int:
         """Queue one request; returns its id.  psi_in (and psi_out, default a
-        new array) are kept referenced until the result is polled."""
+        new array) are kept referenced until the result is polled.  A real
+        psi_in (float64 on a c128 server, float32 on a c64 one) asks for an
+        imaginary-time solve on real storage."""
         import numpy as np
 
-        if not isinstance(psi_in, np.ndarray) or psi_in.dtype != self.np_dtype or psi_in.ndim != 3 \
-                or not psi_in.flags.c_contiguous:
+        real_dt = {C128: np.float64, C64: np.float32}.get(self.dtype)
+        real_state = real_dt is not None and isinstance(psi_in, np.ndarray) and psi_in.dtype == real_dt \
+            and self.np_dtype != real_dt
+        if not isinstance(psi_in, np.ndarray) or (psi_in.dtype != self.np_dtype and not real_state) \
+                or psi_in.ndim != 3 or not psi_in.flags.c_contiguous:
             raise ValueError(f"psi_in must be a C-contiguous {np.dtype(self.np_dtype).name} array (Nz, Ny, Nx)")
         if psi_out is None:
             psi_out = np.empty_like(psi_in)
@@ -608,6 +614,7 @@ class Server:
         r.psi_in = psi_in.ctypes.data
         r.psi_out = psi_out.ctypes.data
         r.tag = int(tag)
+        r.real_state = 1 if real_state else 0
         rid = ctypes.c_uint64()
         _check(lib().gp_server_submit(self._handle, ctypes.byref(r), ctypes.byref(rid)), "gp_server_submit")
         self._held[rid.value] = (psi_in, psi_out)

@@ -123,6 +123,7 @@ struct Live {
     gp_request r;
     double t_submit, t_admit;
     SolveDesc d;
+    gp_dtype dt = GP_C128;        // storage
     int cls = -1, slot = -1;
     size_t off = 0, bytes = 0;
     int64_t steps = 0, next_event = 0;
@@ -134,6 +135,7 @@ struct Live {
 
 struct SClass : ClassShape {
     bool real = false;
+    gp_dtype dt = GP_C128;        // storage of its solves
     std::vector<int> slots;       // resident slots
     int *d_list = nullptr;        // device: the resident slots
     int *d_due = nullptr;         // device: slots with an event this round
@@ -147,9 +149,17 @@ double now_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-bool same_key(const SClass &c, const int64_t g[3], bool real)
+bool same_key(const SClass &c, const int64_t g[3], bool real, gp_dtype dt)
 {
-    return c.real == real && c.grid[0] == g[0] && c.grid[1] == g[1] && c.grid[2] == g[2];
+    return c.real == real && c.dt == dt && c.grid[0] == g[0] && c.grid[1] == g[1] && c.grid[2] == g[2];
+}
+
+// Storage of one request: the server's dtype, or its real counterpart for a
+// real imaginary-time state (same arithmetic type).
+gp_dtype request_dtype(gp_dtype server, const gp_request &r)
+{
+    if (!r.real_state) return server;
+    return server == GP_C128 ? GP_R64 : (server == GP_C64 ? GP_R32 : server);
 }
 
 }  // namespace
@@ -184,6 +194,7 @@ struct gp_server {
     std::vector<int> free_slots;
     int64_t engine_step = 0;
     bool lists_dirty = true;
+    double acc_in = 0.0, acc_out = 0.0, acc_rounds = 0.0;   // published in st at the end of a round
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
@@ -234,10 +245,10 @@ void release(gp_server *S)
 }
 
 // Finds or creates the class of a grid and mode (engine thread).
-hipError_t class_of(gp_server *S, const int64_t grid[3], bool real, int *out)
+hipError_t class_of(gp_server *S, const int64_t grid[3], bool real, gp_dtype dt, int *out)
 {
     for (size_t i = 0; i < S->cls.size(); ++i)
-        if (same_key(S->cls[i], grid, real)) {
+        if (same_key(S->cls[i], grid, real, dt)) {
             *out = (int)i;
             return hipSuccess;
         }
@@ -266,8 +277,9 @@ hipError_t class_of(gp_server *S, const int64_t grid[3], bool real, int *out)
         S->cls.push_back(c);
     }
     SClass &c = S->cls[(size_t)idx];
-    static_cast<ClassShape &>(c) = class_shape(grid, S->dtype);
+    static_cast<ClassShape &>(c) = class_shape(grid, dt);
     c.real = real;
+    c.dt = dt;
     c.slots.clear();
     c.ndue = c.nfresh = 0;
     *out = idx;
@@ -280,7 +292,7 @@ hipError_t stage_solve(gp_server *S, Live &L, const SClass &c, const Footprint &
 {
     unsigned char *blk = S->d_arena + L.off;
     std::vector<unsigned char> tab(f.tables, 0);
-    pack_solve_tables(L.d, c, S->dtype, tab.data());
+    pack_solve_tables(L.d, c, L.dt, tab.data());
     const int s = L.slot;
     auto *xa = reinterpret_cast<gpssc::XBatchArgs<A> *>(S->h_xargs + S->xsz * (size_t)s);
     auto *ya = reinterpret_cast<gpssc::SBatchArgs<A> *>(S->h_yargs + S->ssz * (size_t)s);
@@ -307,7 +319,7 @@ hipError_t stage_solve(gp_server *S, Live &L, const SClass &c, const Footprint &
         {S->d_scales + s, S->h_one, sizeof(double)},
         {S->d_flags + s, S->h_zero, sizeof(int)},
         {S->d_obsargs + s, S->h_obsargs + s, sizeof(gpssc::ObsArgs<double>)},
-        {blk, L.r.psi_in, storage_bytes(S->dtype) * (size_t)L.d.elems},
+        {blk, L.r.psi_in, storage_bytes(L.dt) * (size_t)L.d.elems},
     };
     hipError_t e = hipSuccess;
     for (const Up &u : ups)
@@ -331,12 +343,12 @@ hipError_t upload_lists(gp_server *S)
 
 hipError_t enqueue_step(gp_server *S)
 {
-    const gpssc::Prec prec = static_cast<gpssc::Prec>(S->dtype);
     double *base = reinterpret_cast<double *>(S->d_arena);
     hipError_t e = hipSuccess;
     for (const SClass &c : S->cls) {
         const int n = (int)c.slots.size();
         if (!n) continue;
+        const gpssc::Prec prec = static_cast<gpssc::Prec>(c.dt);
         e = gpssc::launch_nu_x_batch(prec, c.real, c.chunk[0], n, c.nlines, S->d_psis, S->d_xargs, c.d_list,
                                      c.real ? nullptr : S->d_scales, S->stream);
         if (e != hipSuccess) return e;
@@ -376,7 +388,7 @@ hipError_t capture(gp_server *S)
 // Observables sums of the listed slots of one class into sums (per slot).
 hipError_t observe(gp_server *S, const SClass &c, int n, const int *d_slots, double *sums)
 {
-    return gpssc::launch_observables_batch(static_cast<gpssc::Prec>(S->dtype), n, d_slots, S->d_psis, S->d_obsargs,
+    return gpssc::launch_observables_batch(static_cast<gpssc::Prec>(c.dt), n, d_slots, S->d_psis, S->d_obsargs,
                                            (int)c.grid[0], (int)c.grid[1], reinterpret_cast<double *>(S->d_arena),
                                            S->d_obs_off, sums, S->stream);
 }
@@ -395,10 +407,12 @@ void finish(gp_server *S, Live &L, gp_status status, const gp_obs &obs, bool con
     r.t_admit = L.t_admit;
     L.done = true;
     // psi out, then the memory is free
-    hipError_t e = hipMemcpyAsync(L.r.psi_out, S->d_arena + L.off, storage_bytes(S->dtype) * (size_t)L.d.elems,
+    const double tc = now_since(S->t0);
+    hipError_t e = hipMemcpyAsync(L.r.psi_out, S->d_arena + L.off, storage_bytes(L.dt) * (size_t)L.d.elems,
                                   hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess && r.status == GP_OK) r.status = GP_ERR_DEVICE;
+    S->acc_out += now_since(S->t0) - tc;
     S->arena.release(L.off, L.bytes);
     S->free_slots.push_back(L.slot);
     SClass &c = S->cls[(size_t)L.cls];
@@ -469,8 +483,9 @@ bool round_once(gp_server *S)
             // later ones, until it has waited kMaxPass rounds at the head
             size_t slots_left = S->free_slots.size();
             for (auto it = S->queue.begin(); it != S->queue.end() && slots_left > 0;) {
-                const ClassShape shp = class_shape(it->r.grid, S->dtype);
-                const size_t need = footprint(shp, S->dtype, it->r.mode == GP_MODE_REAL).total;
+                const gp_dtype rdt = request_dtype(S->dtype, it->r);
+                const ClassShape shp = class_shape(it->r.grid, rdt);
+                const size_t need = footprint(shp, rdt, it->r.mode == GP_MODE_REAL).total;
                 size_t off = 0;
                 if (S->arena.alloc(need, &off)) {
                     admitted.push_back({*it, off});
@@ -503,18 +518,21 @@ bool round_once(gp_server *S)
         L.d.dt = p.r.dt;
         L.d.g = p.r.g;
         L.d.real = p.r.mode == GP_MODE_REAL;
-        hipError_t e = class_of(S, L.d.grid, L.d.real, &L.cls);
+        L.dt = request_dtype(S->dtype, p.r);
+        hipError_t e = class_of(S, L.d.grid, L.d.real, L.dt, &L.cls);
         if (e != hipSuccess) {
             fail_all(S, e, "allocating a class");
             return false;
         }
         SClass &c = S->cls[(size_t)L.cls];
-        const Footprint f = footprint(c, S->dtype, L.d.real);
+        const Footprint f = footprint(c, L.dt, L.d.real);
         L.bytes = f.total;
         build_solve(L.d, c);
         L.slot = S->free_slots.back();
         S->free_slots.pop_back();
+        const double tc = now_since(S->t0);
         e = arith_f32(S->dtype) ? stage_solve<float>(S, L, c, f) : stage_solve<double>(S, L, c, f);
+        S->acc_in += now_since(S->t0) - tc;
         if (e != hipSuccess) {
             fail_all(S, e, "copying a request in");
             return false;
@@ -536,6 +554,7 @@ bool round_once(gp_server *S)
     for (const Live &L : S->live) q = std::min(q, L.next_event - L.steps);
     for (Live &L : S->live) L.due = L.steps + q == L.next_event;
     for (SClass &c : S->cls) c.ndue = c.nfresh = 0;
+    const double tr = now_since(S->t0);
     hipError_t e = hipSuccess;
     if (S->lists_dirty) {
         e = upload_lists(S);
@@ -568,7 +587,7 @@ bool round_once(gp_server *S)
         e = hipMemcpyAsync(c.d_due, c.h_stage + 2 * ms, sizeof(int) * (size_t)c.ndue, hipMemcpyHostToDevice,
                            S->stream);
         if (e == hipSuccess && !c.real)
-            e = gpssc::launch_scale_batch(static_cast<gpssc::Prec>(S->dtype), c.ndue, c.d_due, S->d_psis,
+            e = gpssc::launch_scale_batch(static_cast<gpssc::Prec>(c.dt), c.ndue, c.d_due, S->d_psis,
                                           c.grid[0] * c.grid[1] * c.grid[2], S->d_scales, S->stream);
         if (e == hipSuccess) e = observe(S, c, c.ndue, c.d_due, S->d_sums);
     }
@@ -585,6 +604,7 @@ bool round_once(gp_server *S)
         fail_all(S, e, "running a round");
         return false;
     }
+    S->acc_rounds += now_since(S->t0) - tr;
     S->engine_step += q;
     int64_t nsteps = 0;
     for (Live &L : S->live) {
@@ -625,6 +645,9 @@ bool round_once(gp_server *S)
     ++S->st.quanta;
     S->st.solve_steps += nsteps;
     S->st.bytes_in_use = S->arena.in_use;
+    S->st.seconds_copy_in = S->acc_in;
+    S->st.seconds_copy_out = S->acc_out;
+    S->st.seconds_rounds = S->acc_rounds;
     return true;
 }
 
@@ -756,8 +779,11 @@ gp_status gp_server_submit(gp_server *S, const gp_request *r, uint64_t *id)
     if (!r->psi_in || !r->psi_out) return fail(GP_ERR_INVALID, "psi_in and psi_out are required");
     if (real_storage(S->dtype) && r->mode != GP_MODE_IMAG)
         return fail(GP_ERR_INVALID, "a server with real storage takes imaginary-time requests only");
-    if (!grid_supported(r->grid, S->dtype)) return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
-    const size_t need = gp_server_request_bytes(r->grid, S->dtype, r->mode);
+    if (r->real_state && (r->mode != GP_MODE_IMAG || S->dtype == GP_C64_F64))
+        return fail(GP_ERR_INVALID, "real_state needs an imaginary-time request on a GP_C128 or GP_C64 server");
+    const gp_dtype rdt = request_dtype(S->dtype, *r);
+    if (!grid_supported(r->grid, rdt)) return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
+    const size_t need = gp_server_request_bytes(r->grid, rdt, r->mode);
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->failed != GP_OK) return fail(S->failed, "the server's engine failed: " + S->fail_msg);
     if (S->stop) return fail(GP_ERR_INVALID, "the server is stopping");

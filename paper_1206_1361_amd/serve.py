@@ -1,7 +1,7 @@
 """Serving load: Poisson arrivals of mixed solve requests against gp_server.
 
     python -m paper_1206_1361_amd.serve [--rate 50] [--seconds 60] [--dtype c64]
-        [--budget-gib 2] [--slots 96] [--check-every 10] [--verify 8]
+        [--budget-gib 2] [--slots 96] [--check-every 10] [--verify 8] [--real-states]
 
 Requests arrive as a seeded Poisson process.  70% are imaginary-time ground
 states (Gaussian start of the request's own trap, stopped when mu moves by
@@ -15,6 +15,8 @@ and copied in by the server at admission; its final state is copied back
 before the result is reported.  Latency = result time - submit time on the
 server's clock.  Prints one JSON line; `--verify N` re-serves N sampled
 requests alone afterwards and checks they give the same bits as in the mix.
+With `--real-states` the ground-state requests send their (real) Gaussian
+as a real array and run on real storage, half the bytes per point.
 """
 from __future__ import annotations
 
@@ -59,9 +61,16 @@ def pct(v, q):
 
 
 def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_every=10, tol=1e-8,
-        imag_cap=20000, real_steps=2000, verify=8, seed=4, log=None) -> dict:
+        imag_cap=20000, real_steps=2000, verify=8, seed=4, real_states=False, graph=True, log=None) -> dict:
     log = log or (lambda m: print(m, file=sys.stderr, flush=True))
     npd = np.complex128 if gp._dtype(dtype) == gp.C128 else np.complex64
+    npr = np.float64 if npd is np.complex128 else np.float32
+
+    def payload(rq):
+        """The request's initial state: real storage for ground states when
+        real_states (their Gaussian start is real)."""
+        real = real_states and rq["kind"] == "imag"
+        return inputs.separable_gaussian(rq["grid"], (DX,) * 3, rq["trap"], npr if real else npd)
     sched = schedule(rate, seconds, seed)
     keep = set(range(0, len(sched), max(1, len(sched) // max(verify, 1)))) if verify else set()
     keep = set(sorted(keep)[:verify])
@@ -69,7 +78,7 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
     stop = threading.Event()
 
     with gp.Server(dtype=dtype, hbm_budget=int(budget_gib * (1 << 30)), max_slots=slots,
-                   check_every=check_every) as srv:
+                   check_every=check_every, graph=graph) as srv:
         def collector():
             while not stop.is_set() or len(results) < len(sched):
                 for r in srv.poll(wait=0.2):
@@ -92,7 +101,7 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
             if now < t0 + rq["t"]:
                 time.sleep(t0 + rq["t"] - now)
             late.append(time.perf_counter() - (t0 + rq["t"]))
-            psi = inputs.separable_gaussian(rq["grid"], (DX,) * 3, rq["trap"], npd)
+            psi = payload(rq)
             srv.submit(psi, psi_out=psi, tag=i, **request_args(rq, tol, imag_cap, real_steps))
             if time.perf_counter() > next_log:
                 st = srv.stats()
@@ -112,7 +121,7 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
             same = 0
             for tag in sorted(keep):
                 rq = sched[tag]
-                psi = inputs.separable_gaussian(rq["grid"], (DX,) * 3, rq["trap"], npd)
+                psi = payload(rq)
                 srv.submit(psi, psi_out=psi, tag=tag, **request_args(rq, tol, imag_cap, real_steps))
                 alone = []
                 while not alone:
@@ -137,7 +146,8 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
     pts = sum(r["steps"] * int(np.prod(q["grid"])) for r, q in zip(res, sched) if r["status"] == 0)
     return {
         "workload": f"serve-poisson-{rate:g}/s-{seconds:g}s", "dtype": dtype,
-        "storage": "complex128" if npd is np.complex128 else "complex64",
+        "storage": ("complex128" if npd is np.complex128 else "complex64") +
+                   (f"; ground states on real {np.dtype(npr).name}" if real_states else ""),
         "reductions": "f64", "requests": len(sched), "completed_ok": len(ok),
         "imag_converged": f"{sum(conv)}/{len(conv)}",
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": round(float(np.mean(lat)), 2) if lat else None,
@@ -147,8 +157,11 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
         "throughput_rps": round(len(ok) / span, 2), "offered_rps": rate,
         "pt_steps_per_s": pts / span, "makespan_s": round(span, 2), "wall_s": round(wall, 2),
         "submit_lateness_ms_p99": pct([1e3 * v for v in late], 99),
+        "engine_seconds": {"copy_in": round(st["seconds_copy_in"], 2), "copy_out": round(st["seconds_copy_out"], 2),
+                           "rounds": round(st["seconds_rounds"], 2)},
         "max_resident": st["max_resident"], "bytes_peak": st["bytes_peak"], "bytes_budget": st["bytes_budget"],
-        "slots": slots, "check_every": check_every, "rounds": st["quanta"], "graph_captures": st["graph_captures"],
+        "slots": slots, "check_every": check_every, "graph": graph, "rounds": st["quanta"],
+        "graph_captures": st["graph_captures"],
         "same_alone_and_in_mix": None if same is None else f"{same}/{len(keep)}",
     }
 
@@ -163,8 +176,12 @@ def main() -> int:
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--verify", type=int, default=8)
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--real-states", action="store_true",
+                    help="ground-state requests carry real states and run on real storage")
+    ap.add_argument("--no-graph", action="store_true", help="launch the rounds' steps without graph replay")
     a = ap.parse_args()
-    out = run(a.rate, a.seconds, a.dtype, a.budget_gib, a.slots, a.check_every, verify=a.verify, seed=a.seed)
+    out = run(a.rate, a.seconds, a.dtype, a.budget_gib, a.slots, a.check_every, verify=a.verify, seed=a.seed,
+              real_states=a.real_states, graph=not a.no_graph)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -179,3 +179,39 @@ def test_submit_checks():
         with pytest.raises(gp.GPNoMemory):
             srv.submit(big, dx=0.3, dt=0.01, trap=(1, 1, 1), g=1.0, steps=10)
         assert srv.drain(5.0)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_real_states_on_real_storage(dtype):
+    """Imaginary-time requests with real states run on real storage beside
+    complex ones; each equals the single plan of its storage type (r32 is
+    bitwise c64 for a real state), alone or in the mix."""
+    npc = np.complex64 if dtype == "c64" else np.complex128
+    npr = np.float32 if dtype == "c64" else np.float64
+    rdt = "r32" if dtype == "c64" else "r64"
+    rqs = requests(6, n=6, dtype=npc)
+    for i, rq in enumerate(rqs):
+        if rq["mode"] == "imag" and i % 2 == 0:
+            rq["psi"] = np.ascontiguousarray(rq["psi"].real).astype(npr)
+    with gp.Server(dtype=dtype, hbm_budget=256 << 20, max_slots=16, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+    for i, rq in enumerate(rqs):
+        real = rq["psi"].dtype == npr
+        ref, robs, steps, conv = plan_reference(rq, rdt if real else dtype)
+        assert got[i]["psi"].dtype == rq["psi"].dtype
+        assert got[i]["steps"] == steps and np.array_equal(got[i]["psi"], ref), i
+        assert got[i]["obs"]["mu"] == robs["mu"], i
+    if dtype == "c64":   # real storage is the complex arithmetic on the real part
+        rq = next(r for r in rqs if r["psi"].dtype == npr)
+        ref_c, _, _, _ = plan_reference(dict(rq, psi=rq["psi"].astype(npc)), "c64")
+        with gp.Server(dtype="c64", hbm_budget=64 << 20, max_slots=4, check_every=K) as srv:
+            submit(srv, rq, 0)
+            r = collect(srv, 1)[0]
+        assert np.array_equal(r["psi"], ref_c.real)
+    with gp.Server(dtype=dtype, hbm_budget=64 << 20, max_slots=4, check_every=K) as srv:
+        bad = next(r for r in rqs if r["mode"] == "real")
+        with pytest.raises(gp.GPInvalid):
+            srv.submit(np.ascontiguousarray(bad["psi"].real).astype(npr), dx=bad["dx"], dt=bad["dt"],
+                       trap=bad["trap"], g=bad["g"], mode="real", steps=10)
