@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gpssc {
 
 // Chunked Thomas layout limits.  A line of n points is cut into `lanes`
@@ -77,6 +79,32 @@ __device__ __forceinline__ S st(cx<A> v)
     } else {
         return (R)v.re;
     }
+}
+
+// Register value of a storage type: cx<A> for complex storage, A itself for
+// real storage (imaginary-time states, whose imaginary parts are zero).
+template <typename S, typename A>
+using value_t = typename std::conditional<storage_traits<S>::complex, cx<A>, A>::type;
+
+template <typename V, typename S>
+__device__ __forceinline__ V ldv(S v)
+{
+    if constexpr (storage_traits<S>::complex)
+        return V{(decltype(V::re))v.x, (decltype(V::re))v.y};
+    else
+        return (V)v;
+}
+
+template <typename S, typename A>
+__device__ __forceinline__ S stv(A v)
+{
+    return (typename storage_traits<S>::real)v;
+}
+
+template <typename S, typename A>
+__device__ __forceinline__ S stv(cx<A> v)
+{
+    return st<S>(v);
 }
 
 template <typename S>

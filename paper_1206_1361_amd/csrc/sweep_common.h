@@ -25,6 +25,25 @@ __device__ __forceinline__ cx<A> kfma(cx<A> coef, cx<A> t, cx<A> v)
     return cx<A>{fma(coef.re, t.re, v.re), fma(coef.re, t.im, v.im)};
 }
 
+// Real values (real storage, imaginary time): the coefficients are real, and
+// these are the real parts of the complex forms above.
+template <bool REAL, typename A>
+__device__ __forceinline__ A kmul(cx<A> coef, A v)
+{
+    static_assert(!REAL, "real values carry imaginary-time states only");
+    return coef.re * v;
+}
+
+template <bool REAL, typename A>
+__device__ __forceinline__ A kfma(cx<A> coef, A t, A v)
+{
+    static_assert(!REAL, "real values carry imaginary-time states only");
+    return fma(coef.re, t, v);
+}
+
+template <typename A>
+__device__ __forceinline__ A cabs2(A a) { return a * a; }
+
 // Right-hand side (1 - tau/2 T) psi at one point from its neighbours:
 //   (1 - kappa) u + kappa/2 (lo + hi) = u + kappa w,  w = (lo + hi)/2 - u,
 // with kappa = dt/(2 dx^2) (imaginary time) or i dt/(2 dx^2) (real time).
@@ -36,20 +55,26 @@ __device__ __forceinline__ cx<A> cn_rhs(A kap, cx<A> lo, cx<A> u, cx<A> hi)
     return cx<A>{fma(kap, w.re, u.re), fma(kap, w.im, u.im)};
 }
 
+template <bool REAL, typename A>
+__device__ __forceinline__ A cn_rhs(A kap, A lo, A u, A hi)
+{
+    static_assert(!REAL, "real values carry imaginary-time states only");
+    return fma(kap, fma((A)0.5, lo + hi, -u), u);
+}
+
 // Passes over one chunk of C points held in registers.  The coefficients
 // are the same at every position (SweepCoef), so they live in scalar
 // registers.
 
 // u <- m (1 - tau/2 T) u, with the points either side of the chunk.
-template <bool REAL, int C, typename A>
-__device__ __forceinline__ void chunk_rhs(cx<A> (&u)[C], cx<A> left, cx<A> right,
-                                          const SweepCoef<A> &k)
+template <bool REAL, int C, typename A, typename V>
+__device__ __forceinline__ void chunk_rhs(V (&u)[C], V left, V right, const SweepCoef<A> &k)
 {
-    cx<A> prev = left;
+    V prev = left;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const cx<A> cur = u[c];
-        const cx<A> rhs = cn_rhs<REAL>(k.kap, prev, cur, c < C - 1 ? u[c + 1] : right);
+        const V cur = u[c];
+        const V rhs = cn_rhs<REAL>(k.kap, prev, cur, c < C - 1 ? u[c + 1] : right);
         prev = cur;
         u[c] = kmul<REAL>(k.m, rhs);
     }
@@ -57,8 +82,8 @@ __device__ __forceinline__ void chunk_rhs(cx<A> (&u)[C], cx<A> left, cx<A> right
 
 // Forward recurrence t <- u_c + a t from carry t; returns the last value
 // and, if STORE, leaves every value in u.
-template <bool REAL, bool STORE, int C, typename A>
-__device__ __forceinline__ cx<A> chunk_forward(cx<A> (&u)[C], cx<A> t, const SweepCoef<A> &k)
+template <bool REAL, bool STORE, int C, typename A, typename V>
+__device__ __forceinline__ V chunk_forward(V (&u)[C], V t, const SweepCoef<A> &k)
 {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -69,8 +94,8 @@ __device__ __forceinline__ cx<A> chunk_forward(cx<A> (&u)[C], cx<A> t, const Swe
 }
 
 // Backward recurrence t <- u_c + a t from the chunk end.
-template <bool REAL, bool STORE, int C, typename A>
-__device__ __forceinline__ cx<A> chunk_backward(cx<A> (&u)[C], cx<A> t, const SweepCoef<A> &k)
+template <bool REAL, bool STORE, int C, typename A, typename V>
+__device__ __forceinline__ V chunk_backward(V (&u)[C], V t, const SweepCoef<A> &k)
 {
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
@@ -82,18 +107,17 @@ __device__ __forceinline__ cx<A> chunk_backward(cx<A> (&u)[C], cx<A> t, const Sw
 
 // Zero the values at positions >= n (the padding after the end of a line),
 // so nothing past the last node feeds the back substitution.
-template <int C, typename A>
-__device__ __forceinline__ void chunk_clear_padding(cx<A> (&u)[C], int pos0, int n)
+template <int C, typename V>
+__device__ __forceinline__ void chunk_clear_padding(V (&u)[C], int pos0, int n)
 {
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        if (pos0 + c >= n) u[c] = cx<A>{0, 0};
+        if (pos0 + c >= n) u[c] = V{};
 }
 
 // Boundary correction x_i = y_i + y_0 zt_i for positions < nzc.
-template <bool REAL, int C, typename A>
-__device__ __forceinline__ void chunk_correct(cx<A> (&u)[C], cx<A> y0, const cx<A> *__restrict__ zt,
-                                              int pos0, int nzc)
+template <bool REAL, int C, typename A, typename V>
+__device__ __forceinline__ void chunk_correct(V (&u)[C], V y0, const cx<A> *__restrict__ zt, int pos0, int nzc)
 {
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -200,6 +224,20 @@ __device__ __forceinline__ cx<A> nu_factor(cx<A> v, A phi)
     return cx<A>{v.re * f, v.im * f};
 }
 
+// Real values: imaginary time only, v * exp(-phi).
+template <bool REAL, typename A>
+__device__ __forceinline__ A nu_factor(A v, A phi)
+{
+    static_assert(!REAL, "real values carry imaginary-time states only");
+    return v * exp_lib<A>(-phi);
+}
+
+// v * s for either value kind.
+template <typename A>
+__device__ __forceinline__ cx<A> vscale(cx<A> v, A s) { return cx<A>{v.re * s, v.im * s}; }
+template <typename A>
+__device__ __forceinline__ A vscale(A v, A s) { return v * s; }
+
 // ---- one x line per wavefront: lane l holds the chunk [l*C, l*C + C) ----
 
 template <typename A>
@@ -213,6 +251,15 @@ __device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d)
 {
     return cx<A>{__shfl_down(v.re, d, kWave), __shfl_down(v.im, d, kWave)};
 }
+
+template <typename A>
+__device__ __forceinline__ A shfl_up_c(A v, int d) { return __shfl_up(v, d, kWave); }
+template <typename A>
+__device__ __forceinline__ A shfl_down_c(A v, int d) { return __shfl_down(v, d, kWave); }
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_c(cx<A> v, int src) { return cx<A>{__shfl(v.re, src, kWave), __shfl(v.im, src, kWave)}; }
+template <typename A>
+__device__ __forceinline__ A shfl_c(A v, int src) { return __shfl(v, src, kWave); }
 
 // LDS slot of line element e: one padding slot after every C elements keeps
 // the chunk-order reads (stride C+1 elements between lanes) off one bank.

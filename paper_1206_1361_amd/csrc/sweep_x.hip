@@ -28,6 +28,7 @@ template <typename S, typename A, int C, bool REAL>
 __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XArgs<A> &a,
                                              const cx<A> *__restrict__ zt, A s, int line)
 {
+    using V = value_t<S, A>;
     const int lane = threadIdx.x;
     const int j = line % a.ny;
     const int k = line / a.ny;
@@ -36,9 +37,9 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
 #pragma unroll
     for (int r = 0; r < C; ++r) buf[xslot<C>(r * kWave + lane)] = row_vals[r];
     __syncthreads();
-    cx<A> u[C];
+    V u[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) u[c] = ld<A>(buf[lane * (C + 1) + c]);
+    for (int c = 0; c < C; ++c) u[c] = ldv<V>(buf[lane * (C + 1) + c]);
 
     // calcnu: pending renormalisation, then exp(-tau (V + g|psi|^2)).
     const A y = ((A)j - a.c0y) * a.dy;
@@ -46,7 +47,7 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
     const A vyz = a.hgy * y * y + a.hgz * z * z;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const cx<A> v = cx<A>{u[c].re * s, u[c].im * s};
+        const V v = vscale(u[c], s);
         const A x = ((A)(pos0 + c) - a.c0x) * a.dx;
         const A theta = fma(a.hgx * x, x, vyz) + a.g * cabs2(v);
         u[c] = nu_factor<REAL>(v, a.dt * theta);   // padding stays 0
@@ -54,47 +55,47 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
 
     // right-hand side with zero ghosts; neighbours across chunk borders come
     // from the adjacent lanes
-    cx<A> left = shfl_up_c(u[C - 1], 1);
-    cx<A> right = shfl_down_c(u[0], 1);
-    if (lane == 0) left = cx<A>{0, 0};
-    if (lane == kWave - 1) right = cx<A>{0, 0};
+    V left = shfl_up_c(u[C - 1], 1);
+    V right = shfl_down_c(u[0], 1);
+    if (lane == 0) left = V{};
+    if (lane == kWave - 1) right = V{};
     chunk_rhs<REAL>(u, left, right, a.k);
 
     // forward: local pass with zero carry, Kogge-Stone across lanes, rerun
-    cx<A> t = chunk_forward<REAL, false>(u, cx<A>{0, 0}, a.k);
+    V t = chunk_forward<REAL, false>(u, V{}, a.k);
 #pragma unroll
     for (int st = 0; st < kMaxStages; ++st) {
         if (st < a.k.nst) {
-            const cx<A> from = shfl_up_c(t, 1 << st);
+            const V from = shfl_up_c(t, 1 << st);
             if (lane >= (1 << st)) t = kfma<REAL>(a.k.stage[st], from, t);
         }
     }
     t = shfl_up_c(t, 1);
-    if (lane == 0) t = cx<A>{0, 0};
+    if (lane == 0) t = V{};
     chunk_forward<REAL, true>(u, t, a.k);
     if (a.nx < kWave * C) chunk_clear_padding(u, pos0, a.nx);
 
     // backward: the same from the right
-    t = chunk_backward<REAL, false>(u, cx<A>{0, 0}, a.k);
+    t = chunk_backward<REAL, false>(u, V{}, a.k);
 #pragma unroll
     for (int st = 0; st < kMaxStages; ++st) {
         if (st < a.k.nst) {
-            const cx<A> from = shfl_down_c(t, 1 << st);
+            const V from = shfl_down_c(t, 1 << st);
             if (lane + (1 << st) < kWave) t = kfma<REAL>(a.k.stage[st], from, t);
         }
     }
     t = shfl_down_c(t, 1);
-    if (lane == kWave - 1) t = cx<A>{0, 0};
+    if (lane == kWave - 1) t = V{};
     chunk_backward<REAL, true>(u, t, a.k);
 
     // boundary correction from the first node
-    const cx<A> y0 = cx<A>{__shfl(u[0].re, 0, kWave), __shfl(u[0].im, 0, kWave)};
+    const V y0 = shfl_c(u[0], 0);
     if (pos0 < a.k.nzc) chunk_correct<REAL>(u, y0, zt, pos0, a.k.nzc);
 
     // chunk order -> LDS -> row order
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < C; ++c) buf[lane * (C + 1) + c] = st<S>(u[c]);
+    for (int c = 0; c < C; ++c) buf[lane * (C + 1) + c] = stv<S>(u[c]);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < C; ++r) row_vals[r] = buf[xslot<C>(r * kWave + lane)];
@@ -200,8 +201,9 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
     case PREC_C64: GP_XB_PREC(float2, float)
     case PREC_C64_F64: GP_XB_PREC(float2, double)
     case PREC_C128: GP_XB_PREC(double2, double)
-    case PREC_R64: GP_XB_PREC(double, double)
-    case PREC_R32: GP_XB_PREC(float, float)
+    // real storage: imaginary time only (real time was refused above)
+    case PREC_R64: return launch_batch_c<double, double, false>(chunk, nact, nlines, psis, args, active, scales, stream);
+    case PREC_R32: return launch_batch_c<float, float, false>(chunk, nact, nlines, psis, args, active, scales, stream);
     }
 #undef GP_XB_PREC
     return hipErrorInvalidValue;
@@ -244,8 +246,9 @@ hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, 
     case PREC_C64: GP_X_PREC(float2, float)
     case PREC_C64_F64: GP_X_PREC(float2, double)
     case PREC_C128: GP_X_PREC(double2, double)
-    case PREC_R64: GP_X_PREC(double, double)
-    case PREC_R32: GP_X_PREC(float, float)
+    // real storage: imaginary time only (real time was refused above)
+    case PREC_R64: return launch_c<double, double, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
+    case PREC_R32: return launch_c<float, float, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
     }
 #undef GP_X_PREC
     return hipErrorInvalidValue;

@@ -24,12 +24,13 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
                                            const cx<A> *__restrict__ zt, double *__restrict__ partials,
                                            unsigned char *smem_raw, int tile, int col0, int outer)
 {
+    using V = value_t<S, A>;
     const int XT = blockDim.x;
     const int P = blockDim.y;
     const int tx = threadIdx.x;
     const int pc = threadIdx.y;
-    cx<A> *b0 = reinterpret_cast<cx<A> *>(smem_raw);
-    cx<A> *b1 = b0 + P * XT;
+    V *b0 = reinterpret_cast<V *>(smem_raw);
+    V *b1 = b0 + P * XT;
     const int me = pc * XT + tx;
 
     const int i = col0 + tx;
@@ -38,15 +39,15 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     const bool full = act && pos0 + C <= a.n;   // whole chunk inside the line
     S *base = psi + (int64_t)outer * a.outer_stride + i + (int64_t)pos0 * a.stride;
 
-    cx<A> u[C];
+    V u[C];
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = ld<A>(stream_load(base + (int64_t)c * a.stride));
+        for (int c = 0; c < C; ++c) u[c] = ldv<V>(stream_load(base + (int64_t)c * a.stride));
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            u[c] = cx<A>{0, 0};
-            if (act && pos0 + c < a.n) u[c] = ld<A>(stream_load(base + (int64_t)c * a.stride));
+            u[c] = V{};
+            if (act && pos0 + c < a.n) u[c] = ldv<V>(stream_load(base + (int64_t)c * a.stride));
         }
     }
 
@@ -54,15 +55,15 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     b0[me] = u[0];
     b1[me] = u[C - 1];
     __syncthreads();
-    const cx<A> zero = cx<A>{0, 0};
-    const cx<A> left = pc > 0 ? b1[me - XT] : zero;
-    const cx<A> right = pc < P - 1 ? b0[me + XT] : zero;
+    const V zero = V{};
+    const V left = pc > 0 ? b1[me - XT] : zero;
+    const V right = pc < P - 1 ? b0[me + XT] : zero;
     chunk_rhs<REAL>(u, left, right, a.k);
 
     // forward: local pass, Kogge-Stone over the chunks through LDS, rerun
-    cx<A> t = chunk_forward<REAL, false>(u, zero, a.k);
+    V t = chunk_forward<REAL, false>(u, zero, a.k);
     __syncthreads();  // every thread has read its neighbours from b0/b1
-    cx<A> *cur = b0, *nxt = b1;
+    V *cur = b0, *nxt = b1;
     cur[me] = t;
     __syncthreads();
 #pragma unroll
@@ -72,7 +73,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
             if (pc >= d) t = kfma<REAL>(a.k.stage[stg], cur[me - d * XT], t);
             nxt[me] = t;
             __syncthreads();
-            cx<A> *tmp = cur; cur = nxt; nxt = tmp;
+            V *tmp = cur; cur = nxt; nxt = tmp;
         }
     }
     t = pc > 0 ? cur[me - XT] : zero;
@@ -84,7 +85,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     __syncthreads();  // every thread has read its forward carry
     nxt[me] = t;
     __syncthreads();
-    { cx<A> *tmp = cur; cur = nxt; nxt = tmp; }
+    { V *tmp = cur; cur = nxt; nxt = tmp; }
 #pragma unroll
     for (int stg = 0; stg < kMaxStages; ++stg) {
         if (stg < a.k.nst) {
@@ -92,7 +93,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
             if (pc + d < P) t = kfma<REAL>(a.k.stage[stg], cur[me + d * XT], t);
             nxt[me] = t;
             __syncthreads();
-            cx<A> *tmp = cur; cur = nxt; nxt = tmp;
+            V *tmp = cur; cur = nxt; nxt = tmp;
         }
     }
     t = pc < P - 1 ? cur[me + XT] : zero;
@@ -106,11 +107,11 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
 
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) stream_store(base + (int64_t)c * a.stride, st<S>(u[c]));
+        for (int c = 0; c < C; ++c) stream_store(base + (int64_t)c * a.stride, stv<S>(u[c]));
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (act && pos0 + c < a.n) stream_store(base + (int64_t)c * a.stride, st<S>(u[c]));
+            if (act && pos0 + c < a.n) stream_store(base + (int64_t)c * a.stride, stv<S>(u[c]));
     }
 
     if (NORM) {
@@ -124,7 +125,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
                 // rounded term by term (no fused multiply-add), the same for
                 // complex and real storage
 #pragma clang fp contract(off)
-                const S v = st<S>(u[c]);
+                const S v = stv<S>(u[c]);
                 acc += sre(v) * sre(v) + sim(v) * sim(v);
             }
         }
@@ -220,8 +221,13 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lan
     case PREC_C64: GP_SB_PREC(float2, float)
     case PREC_C64_F64: GP_SB_PREC(float2, double)
     case PREC_C128: GP_SB_PREC(double2, double)
-    case PREC_R64: GP_SB_PREC(double, double)
-    case PREC_R32: GP_SB_PREC(float, float)
+    // real storage: imaginary time only (real time was refused above)
+    case PREC_R64:
+        return launch_batch_t<double, double, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active,
+                                                     partials, part_off, stream);
+    case PREC_R32:
+        return launch_batch_t<float, float, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active,
+                                                   partials, part_off, stream);
     }
 #undef GP_SB_PREC
     return hipErrorInvalidValue;
@@ -271,8 +277,9 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, i
     case PREC_C64: GP_S_PREC(float2, float)
     case PREC_C64_F64: GP_S_PREC(float2, double)
     case PREC_C128: GP_S_PREC(double2, double)
-    case PREC_R64: GP_S_PREC(double, double)
-    case PREC_R32: GP_S_PREC(float, float)
+    // real storage: imaginary time only (real time was refused above)
+    case PREC_R64: return launch_t<double, double, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
+    case PREC_R32: return launch_t<float, float, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
     }
 #undef GP_S_PREC
     return hipErrorInvalidValue;
