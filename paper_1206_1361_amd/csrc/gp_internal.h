@@ -304,11 +304,24 @@ struct ObsArgs {
 // equal gp_dtype's.
 enum Prec { PREC_C128 = 0, PREC_C64 = 1, PREC_C64_F64 = 2, PREC_R64 = 3, PREC_R32 = 4 };
 
+// x lines one wavefront solves together.  A short line (chunks of a few
+// points) leaves its wavefront waiting on latency, so a wavefront interleaves
+// up to 4 (chunks of 1-2 points) or 2 (3-4 points) of them -- but only while
+// at least 4096 wavefronts (about four per SIMD) remain for the nlines lines,
+// since small grids need the wavefronts more than the overlap.
+constexpr int x_max_lines_per_wave(int chunk) { return chunk <= 2 ? 4 : chunk <= 4 ? 2 : 1; }
+constexpr int x_lines_per_wave(int chunk, int64_t nlines)
+{
+    int l = 1;
+    while (l < x_max_lines_per_wave(chunk) && nlines >= (int64_t)2 * l * 4096) l *= 2;
+    return l;
+}
+
 // calcnu + calclux.  zt: boundary correction by position (complex, the
 // arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
 // partials: NULL or one double per x line (sum |psi|^2 of its output).
-// nblocks: one-wavefront blocks to launch (each loops over lines; 0 or >= the
-// line count = one per line).
+// nblocks: one-wavefront blocks to launch (each takes x_lines_per_wave(chunk,
+// ny nz) lines at a time and loops; 0 or enough for every line = one pass).
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
                        const void *zt, const double *scale, double *partials, hipStream_t stream);
 

@@ -592,7 +592,8 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
     // step and their load, compute and store phases overlap.  (A grid of
     // resident blocks looping over the work keeps them in lockstep and was
     // measured slower.)
-    p->x_blocks = (int)(grid[1] * grid[2]);
+    const int64_t xl = gpssc::x_lines_per_wave(p->ax[0].chunk, grid[1] * grid[2]);
+    p->x_blocks = (int)((grid[1] * grid[2] + xl - 1) / xl);
     p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
     p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
     *out = p;

@@ -47,9 +47,13 @@ __device__ __forceinline__ A cabs2(A a) { return a * a; }
 // Right-hand side (1 - tau/2 T) psi at one point from its neighbours:
 //   (1 - kappa) u + kappa/2 (lo + hi) = u + kappa w,  w = (lo + hi)/2 - u,
 // with kappa = dt/(2 dx^2) (imaginary time) or i dt/(2 dx^2) (real time).
+// lo + hi is rounded on its own: the compiler may not fuse it with the
+// multiplication that produced a neighbour, whose choice would otherwise
+// depend on the shape of the surrounding code.
 template <bool REAL, typename A>
 __device__ __forceinline__ cx<A> cn_rhs(A kap, cx<A> lo, cx<A> u, cx<A> hi)
 {
+#pragma clang fp contract(off)
     const cx<A> w = cx<A>{fma((A)0.5, lo.re + hi.re, -u.re), fma((A)0.5, lo.im + hi.im, -u.im)};
     if (REAL) return cx<A>{fma(-kap, w.im, u.re), fma(kap, w.re, u.im)};
     return cx<A>{fma(kap, w.re, u.re), fma(kap, w.im, u.im)};
@@ -58,6 +62,7 @@ __device__ __forceinline__ cx<A> cn_rhs(A kap, cx<A> lo, cx<A> u, cx<A> hi)
 template <bool REAL, typename A>
 __device__ __forceinline__ A cn_rhs(A kap, A lo, A u, A hi)
 {
+#pragma clang fp contract(off)
     static_assert(!REAL, "real values carry imaginary-time states only");
     return fma(kap, fma((A)0.5, lo + hi, -u), u);
 }
@@ -232,6 +237,18 @@ __device__ __forceinline__ A nu_factor(A v, A phi)
     return v * exp_lib<A>(-phi);
 }
 
+// calcnu exponent theta = V(x, y, z) + g |v|^2 from the (y, z) trap part of
+// the line, each rounding written out (no contraction left to the compiler),
+// so a real state held as real or as complex values rounds the same way in
+// every kernel shape.
+template <typename A>
+__device__ __forceinline__ A trap_yz(A hgy, A y, A hgz, A z) { return fma(hgy * y, y, hgz * z * z); }
+template <typename A, typename V>
+__device__ __forceinline__ A nu_theta(A hgx, A x, A vyz, A g, V v)
+{
+    return fma(g, cabs2(v), fma(hgx * x, x, vyz));
+}
+
 // v * s for either value kind.
 template <typename A>
 __device__ __forceinline__ cx<A> vscale(cx<A> v, A s) { return cx<A>{v.re * s, v.im * s}; }
@@ -278,6 +295,4 @@ __device__ __forceinline__ void load_x_row(S (&v)[C], const S *__restrict__ row,
     }
 }
 
-// One wavefront per block; block b solves lines b, b + G, ... (G =
-// gridDim.x).  The plan launches one block per line.
 }  // namespace gpssc

@@ -51,12 +51,12 @@ calcnu_lur_kernel(S *__restrict__ psi, const RadialArgs<A> ra, const double *__r
     const A s = scale ? (A)(*scale) : (A)1;
     const A y = ((A)j - a.c0y) * a.dy;
     const A z = ((A)k - a.c0z) * a.dz;
-    const A vyz = a.hgy * y * y + a.hgz * z * z;
+    const A vyz = trap_yz(a.hgy, y, a.hgz, z);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const cx<A> w = cx<A>{u[c].re * s, u[c].im * s};
         const A x = ((A)(pos0 + c) - a.c0x) * a.dx;
-        const A theta = fma(a.hgx * x, x, vyz) + a.g * cabs2(w);
+        const A theta = nu_theta(a.hgx, x, vyz, a.g, w);
         u[c] = nu_factor<REAL>(w, a.dt * theta);
     }
 

@@ -23,7 +23,11 @@
 namespace gpssc {
 
 // One x line: psi values in row order (element r*64 + lane) -> solved line,
-// in row order, written back through the same LDS buffer.
+// in row order, written back through the same LDS buffer.  solve_x_lines
+// below runs the same steps on several lines at once; this one-line form is
+// kept apart because at 8-point FP64 chunks its register allocation stays
+// within 128 VGPRs (four wavefronts per SIMD) where the several-line form's
+// does not.
 template <typename S, typename A, int C, bool REAL>
 __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XArgs<A> &a,
                                              const cx<A> *__restrict__ zt, A s, int line)
@@ -44,12 +48,12 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
     // calcnu: pending renormalisation, then exp(-tau (V + g|psi|^2)).
     const A y = ((A)j - a.c0y) * a.dy;
     const A z = ((A)k - a.c0z) * a.dz;
-    const A vyz = a.hgy * y * y + a.hgz * z * z;
+    const A vyz = trap_yz(a.hgy, y, a.hgz, z);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const V v = vscale(u[c], s);
         const A x = ((A)(pos0 + c) - a.c0x) * a.dx;
-        const A theta = fma(a.hgx * x, x, vyz) + a.g * cabs2(v);
+        const A theta = nu_theta(a.hgx, x, vyz, a.g, v);
         u[c] = nu_factor<REAL>(v, a.dt * theta);   // padding stays 0
     }
 
@@ -101,6 +105,143 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
     for (int r = 0; r < C; ++r) row_vals[r] = buf[xslot<C>(r * kWave + lane)];
 }
 
+// L x lines at once: psi values in row order (line l, element r*64 + lane)
+// -> solved lines, in row order, written back through LDS (one slice of
+// 64*C + 64 elements per line).  The lines are independent; a wavefront runs
+// them in one instruction stream so that their loads, shuffles and LDS
+// round trips overlap, and every line sees exactly the arithmetic of a line
+// solved alone.
+// args_of(l): the XArgs of line l's grid (sizes, trap, coefficients).
+template <typename A>
+struct XLine {
+    const cx<A> *zt;           // boundary correction of the line's grid
+    A s;                       // pending renormalisation factor
+    int line;                  // j + ny k
+};
+
+template <typename S, typename A, int C, int L, bool REAL, typename ArgsOf, typename LineOf>
+__device__ __forceinline__ void solve_x_lines(S (&rows)[L][C], S *buf, ArgsOf args_of, LineOf ln)
+{
+    using V = value_t<S, A>;
+    constexpr int SL = kWave * C + kWave;
+    const int lane = threadIdx.x;
+    const int pos0 = lane * C;
+
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+        for (int r = 0; r < C; ++r) buf[l * SL + xslot<C>(r * kWave + lane)] = rows[l][r];
+    __syncthreads();
+    V u[L][C];
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+        for (int c = 0; c < C; ++c) u[l][c] = ldv<V>(buf[l * SL + lane * (C + 1) + c]);
+
+    // calcnu: pending renormalisation, then exp(-tau (V + g|psi|^2)).
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const XArgs<A> &a = args_of(l);
+        const int j = ln(l).line % a.ny;
+        const int k = ln(l).line / a.ny;
+        const A y = ((A)j - a.c0y) * a.dy;
+        const A z = ((A)k - a.c0z) * a.dz;
+        const A vyz = trap_yz(a.hgy, y, a.hgz, z);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const V v = vscale(u[l][c], ln(l).s);
+            const A x = ((A)(pos0 + c) - a.c0x) * a.dx;
+            const A theta = nu_theta(a.hgx, x, vyz, a.g, v);
+            u[l][c] = nu_factor<REAL>(v, a.dt * theta);   // padding stays 0
+        }
+    }
+
+    // right-hand side with zero ghosts; neighbours across chunk borders come
+    // from the adjacent lanes
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        V left = shfl_up_c(u[l][C - 1], 1);
+        V right = shfl_down_c(u[l][0], 1);
+        if (lane == 0) left = V{};
+        if (lane == kWave - 1) right = V{};
+        chunk_rhs<REAL>(u[l], left, right, args_of(l).k);
+    }
+
+    // forward: local pass with zero carry, Kogge-Stone across lanes, rerun
+    V t[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) t[l] = chunk_forward<REAL, false>(u[l], V{}, args_of(l).k);
+#pragma unroll
+    for (int st = 0; st < kMaxStages; ++st) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (st < args_of(l).k.nst) {
+                const V from = shfl_up_c(t[l], 1 << st);
+                if (lane >= (1 << st)) t[l] = kfma<REAL>(args_of(l).k.stage[st], from, t[l]);
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        t[l] = shfl_up_c(t[l], 1);
+        if (lane == 0) t[l] = V{};
+        chunk_forward<REAL, true>(u[l], t[l], args_of(l).k);
+        if (args_of(l).nx < kWave * C) chunk_clear_padding(u[l], pos0, args_of(l).nx);
+    }
+
+    // backward: the same from the right
+#pragma unroll
+    for (int l = 0; l < L; ++l) t[l] = chunk_backward<REAL, false>(u[l], V{}, args_of(l).k);
+#pragma unroll
+    for (int st = 0; st < kMaxStages; ++st) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (st < args_of(l).k.nst) {
+                const V from = shfl_down_c(t[l], 1 << st);
+                if (lane + (1 << st) < kWave) t[l] = kfma<REAL>(args_of(l).k.stage[st], from, t[l]);
+            }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        t[l] = shfl_down_c(t[l], 1);
+        if (lane == kWave - 1) t[l] = V{};
+        chunk_backward<REAL, true>(u[l], t[l], args_of(l).k);
+    }
+
+    // boundary correction from the first node
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const V y0 = shfl_c(u[l][0], 0);
+        if (pos0 < args_of(l).k.nzc) chunk_correct<REAL>(u[l], y0, ln(l).zt, pos0, args_of(l).k.nzc);
+    }
+
+    // chunk order -> LDS -> row order
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+        for (int c = 0; c < C; ++c) buf[l * SL + lane * (C + 1) + c] = stv<S>(u[l][c]);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+        for (int r = 0; r < C; ++r) rows[l][r] = buf[l * SL + xslot<C>(r * kWave + lane)];
+}
+
+template <typename S, int C>
+__device__ __forceinline__ void store_x_row(S *__restrict__ row, const S (&v)[C], int nx)
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+        const int e = r * kWave + lane;
+        if (e < nx) stream_store(row + e, v[r]);
+    }
+}
+
+// One wavefront per block; block b solves lines b, b + G, ... (G =
+// gridDim.x).
 // partials: NULL, or one double per line receiving sum |psi|^2 of the stored
 // line (the norm partials of imaginary time when x is the only variable),
 // summed per lane in row order, then over the lanes by a fixed tree.
@@ -140,42 +281,109 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
     }
 }
 
-// Batched: block b advances line b % nlines of solve active[b / nlines].
-template <typename S, typename A, int C, bool REAL>
+// Short lines (chunk <= 4): one wavefront per block; block b solves lines
+// bL .. bL + L - 1 together, then the lines G L further on (G = gridDim.x).
+// Past the last line a slot solves the last line again and stores nothing.
+// partials as in calcnu_lux_kernel.
+template <typename S, typename A, int C, int L, bool REAL>
+__global__ void __launch_bounds__(kWave)
+calcnu_lux_lines_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict__ zt,
+                        const double *__restrict__ scale, double *__restrict__ partials)
+{
+    __shared__ S buf[L * (kWave * C + kWave)];
+    const int lane = threadIdx.x;
+    const int nx = a.nx;
+    const int nlines = a.ny * a.nz;
+    const A s = scale ? (A)(*scale) : (A)1;
+    for (int base = blockIdx.x * L; base < nlines; base += gridDim.x * L) {
+        auto ln = [&](int l) { return XLine<A>{zt, s, min(base + l, nlines - 1)}; };
+        S v[L][C];
+#pragma unroll
+        for (int l = 0; l < L; ++l) load_x_row(v[l], psi + (int64_t)ln(l).line * nx, nx);
+        solve_x_lines<S, A, C, L, REAL>(v, buf, [&](int) -> const XArgs<A> & { return a; }, ln);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            if (base + l >= nlines) break;
+            store_x_row(psi + (int64_t)ln(l).line * nx, v[l], nx);
+            if (partials) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    if (r * kWave + lane < nx) {
+#pragma clang fp contract(off)
+                        acc += sre(v[l][r]) * sre(v[l][r]) + sim(v[l][r]) * sim(v[l][r]);
+                    }
+                }
+#pragma unroll
+                for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_down(acc, d, kWave);
+                if (lane == 0) partials[ln(l).line] = acc;
+            }
+        }
+        __syncthreads();  // buf is free for the next lines
+    }
+}
+
+// Batched: block b advances the lines g = bL .. bL + L - 1 of the list of
+// active solves, line g % nlines of solve active[g / nlines], for g below
+// total = nact * nlines (past it, the last line again, not stored).
+template <typename S, typename A, int C, int L, bool REAL>
 __global__ void __launch_bounds__(kWave)
 calcnu_lux_batch_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
-                        const int *__restrict__ active, int nlines, const double *__restrict__ scales)
+                        const int *__restrict__ active, int nlines, int total,
+                        const double *__restrict__ scales)
 {
-    __shared__ S buf[kWave * C + kWave];
-    const int lane = threadIdx.x;
-    const int slot = blockIdx.x / nlines;
-    const int line = blockIdx.x - slot * nlines;
-    const int si = active[slot];
-    const XArgs<A> &a = args[si].x;
-    const A s = scales ? (A)scales[si] : (A)1;
-    S *row = psis[si] + (int64_t)line * a.nx;
-    S v[C];
-    load_x_row(v, row, a.nx);
-    solve_x_line<S, A, C, REAL>(v, buf, a, args[si].zt, s, line);
+    __shared__ S buf[L * (kWave * C + kWave)];
+    const int g0 = blockIdx.x * L;
+    const XArgs<A> *ap[L];
+    XLine<A> ln[L];
+    S *rows[L];
+    S v[L][C];
 #pragma unroll
-    for (int r = 0; r < C; ++r) {
-        const int e = r * kWave + lane;
-        if (e < a.nx) stream_store(row + e, v[r]);
+    for (int l = 0; l < L; ++l) {
+        const int g = min(g0 + l, total - 1);
+        const int slot = g / nlines;
+        const int si = active[slot];
+        ap[l] = &args[si].x;
+        ln[l] = XLine<A>{args[si].zt, scales ? (A)scales[si] : (A)1, g - slot * nlines};
+        rows[l] = psis[si] + (int64_t)ln[l].line * ap[l]->nx;
+        load_x_row(v[l], rows[l], ap[l]->nx);
     }
+    solve_x_lines<S, A, C, L, REAL>(v, buf, [&](int l) -> const XArgs<A> & { return *ap[l]; }, [&](int l) { return ln[l]; });
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+        if (g0 + l < total) store_x_row(rows[l], v[l], ap[l]->nx);
+}
+
+// Launch the L-line form with chunk C (L at most x_max_lines_per_wave(C)).
+template <typename S, typename A, int C, bool REAL>
+static void launch_batch_l(int L, dim3 grid, hipStream_t stream, S *const *p, const XBatchArgs<A> *a,
+                           const int *active, int nlines, int total, const double *scales)
+{
+    constexpr int LM = x_max_lines_per_wave(C);
+    if (LM >= 4 && L == 4)
+        hipLaunchKernelGGL((calcnu_lux_batch_kernel<S, A, C, (LM >= 4 ? 4 : 1), REAL>), grid, dim3(kWave), 0,
+                           stream, p, a, active, nlines, total, scales);
+    else if (LM >= 2 && L == 2)
+        hipLaunchKernelGGL((calcnu_lux_batch_kernel<S, A, C, (LM >= 2 ? 2 : 1), REAL>), grid, dim3(kWave), 0,
+                           stream, p, a, active, nlines, total, scales);
+    else
+        hipLaunchKernelGGL((calcnu_lux_batch_kernel<S, A, C, 1, REAL>), grid, dim3(kWave), 0, stream,
+                           p, a, active, nlines, total, scales);
 }
 
 template <typename S, typename A, bool REAL>
 static hipError_t launch_batch_c(int chunk, int nact, int nlines, void *const *psis, const void *args,
                                  const int *active, const double *scales, hipStream_t stream)
 {
-    const dim3 grid((unsigned)((int64_t)nact * nlines));
-    const dim3 block(kWave);
+    const int64_t total = (int64_t)nact * nlines;
+    if (total > INT32_MAX) return hipErrorInvalidValue;
+    const int L = x_lines_per_wave(chunk, total);
+    const dim3 grid((unsigned)((total + L - 1) / L));
     S *const *p = reinterpret_cast<S *const *>(psis);
     const XBatchArgs<A> *a = static_cast<const XBatchArgs<A> *>(args);
-#define GP_XB_CASE(CC)                                                                        \
-    case CC:                                                                                  \
-        hipLaunchKernelGGL((calcnu_lux_batch_kernel<S, A, CC, REAL>), grid, block, 0, stream,  \
-                           p, a, active, nlines, scales);                                     \
+#define GP_XB_CASE(CC)                                                                    \
+    case CC:                                                                              \
+        launch_batch_l<S, A, CC, REAL>(L, grid, stream, p, a, active, nlines, (int)total, scales); \
         break;
     switch (chunk) {
         GP_XB_CASE(1) GP_XB_CASE(2) GP_XB_CASE(3) GP_XB_CASE(4)
@@ -209,21 +417,45 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
     return hipErrorInvalidValue;
 }
 
+// Launch the L-line form (chunk <= 4) or the one-line kernel (chunk >= 5).
+template <typename S, typename A, int C, bool REAL>
+static void launch_plain_l(int L, dim3 grid, hipStream_t stream, S *p, const XArgs<A> &a, const cx<A> *z,
+                           const double *scale, double *partials)
+{
+    constexpr int LM = x_max_lines_per_wave(C);
+    if constexpr (LM == 1) {
+        hipLaunchKernelGGL((calcnu_lux_kernel<S, A, C, REAL>), grid, dim3(kWave), 0, stream,
+                           p, a, z, scale, partials);
+    } else {
+        if (LM >= 4 && L == 4)
+            hipLaunchKernelGGL((calcnu_lux_lines_kernel<S, A, C, (LM >= 4 ? 4 : 1), REAL>), grid, dim3(kWave), 0,
+                               stream, p, a, z, scale, partials);
+        else if (L == 2)
+            hipLaunchKernelGGL((calcnu_lux_lines_kernel<S, A, C, 2, REAL>), grid, dim3(kWave), 0, stream,
+                               p, a, z, scale, partials);
+        else
+            hipLaunchKernelGGL((calcnu_lux_lines_kernel<S, A, C, 1, REAL>), grid, dim3(kWave), 0, stream,
+                               p, a, z, scale, partials);
+    }
+}
+
 template <typename S, typename A, bool REAL>
 static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, const void *zt,
                            const double *scale, double *partials, hipStream_t stream)
 {
     const XArgs<A> &a = *static_cast<const XArgs<A> *>(args);
     const int nlines = a.ny * a.nz;
-    const dim3 grid((unsigned)(nblocks > 0 && nblocks < nlines ? nblocks : nlines));
-    const dim3 block(kWave);
+    const int L = x_lines_per_wave(chunk, nlines);
+    const int need = (nlines + L - 1) / L;
+    const dim3 grid((unsigned)(nblocks > 0 && nblocks < need ? nblocks : need));
     S *p = static_cast<S *>(psi);
     const cx<A> *z = static_cast<const cx<A> *>(zt);
-#define GP_X_CASE(CC)                                                                  \
-    case CC:                                                                           \
-        hipLaunchKernelGGL((calcnu_lux_kernel<S, A, CC, REAL>), grid, block, 0, stream, \
-                           p, a, z, scale, partials);                                  \
+#define GP_X_CASE(CC)                                                                   \
+    case CC:                                                                            \
+        launch_plain_l<S, A, CC, REAL>(L, grid, stream, p, a, z, scale, partials);       \
         break;
+    static_assert(x_max_lines_per_wave(4) == 2 && x_max_lines_per_wave(5) == 1,
+                  "several-line kernels up to chunk 4, the one-line kernel from chunk 5 on");
     switch (chunk) {
         GP_X_CASE(1) GP_X_CASE(2) GP_X_CASE(3) GP_X_CASE(4)
         GP_X_CASE(5) GP_X_CASE(6) GP_X_CASE(7) GP_X_CASE(8)
