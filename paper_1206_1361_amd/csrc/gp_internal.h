@@ -139,16 +139,20 @@ __device__ __forceinline__ double sim(S v)
         return 0.0;
 }
 
-// v * s componentwise in the storage precision.
+// v * s componentwise: the product formed in FP64 and rounded once to the
+// storage type.  (Rounding s to float first would move every element of a
+// float state by the same relative amount, up to 2^-24, and the norm by
+// twice that.)
 template <typename S>
-__device__ __forceinline__ S sscale(S v, typename storage_traits<S>::real s)
+__device__ __forceinline__ S sscale(S v, double s)
 {
+    using R = typename storage_traits<S>::real;
     if constexpr (storage_traits<S>::complex) {
-        v.x *= s;
-        v.y *= s;
+        v.x = (R)((double)v.x * s);
+        v.y = (R)((double)v.y * s);
         return v;
     } else {
-        return v * s;
+        return (R)((double)v * s);
     }
 }
 
@@ -222,6 +226,40 @@ __device__ __forceinline__ void stream_store(S *p, S val)
         else
             *p = val;
     }
+}
+
+// Two neighbouring complex64 columns handled by one thread of the y/z
+// sweeps: one 16-byte access per row, as complex128 takes, for the FP32
+// arithmetic of complex64.  The two columns never mix; every operation acts
+// on each of them exactly as on a column of its own.
+template <typename A>
+struct cx2 {
+    cx<A> p, q;
+};
+
+typedef float pair4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ cx2<float> stream_load_pair(const float2 *at)
+{
+    pair4_t v;
+    if (GPSSC_NT_LOAD)
+        v = __builtin_nontemporal_load(reinterpret_cast<const pair4_t *>(at));
+    else
+        v = *reinterpret_cast<const pair4_t *>(at);
+    return cx2<float>{cx<float>{v.x, v.y}, cx<float>{v.z, v.w}};
+}
+
+__device__ __forceinline__ void stream_store_pair(float2 *at, cx2<float> u)
+{
+    pair4_t v;
+    v.x = u.p.re;
+    v.y = u.p.im;
+    v.z = u.q.re;
+    v.w = u.q.im;
+    if (GPSSC_NT_STORE)
+        __builtin_nontemporal_store(v, reinterpret_cast<pair4_t *>(at));
+    else
+        *reinterpret_cast<pair4_t *>(at) = v;
 }
 
 // Launch arguments of the calcnu + calclux kernel.
@@ -325,11 +363,13 @@ constexpr int x_lines_per_wave(int chunk, int64_t nlines)
 hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
                        const void *zt, const double *scale, double *partials, hipStream_t stream);
 
-// calcluy / calcluz over ceil(nx/xt) x nouter tiles.  nblocks: blocks to
-// launch (each loops over tiles; 0 or >= the tile count = one per tile).
-// zt: boundary correction by position.  partials: NULL, or nx * nouter
-// doubles: sum |psi|^2 of each line's output, at outer * nx + column.
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, int nblocks,
+// calcluy / calcluz over ceil(nx/(xt cols)) x nouter tiles.  cols: columns
+// per thread, 1, or 2 for complex64 with FP32 arithmetic (then nx and both
+// strides must be even and psi 16-byte aligned).  nblocks: blocks to launch
+// (each loops over tiles; 0 or >= the tile count = one per tile).  zt:
+// boundary correction by position.  partials: NULL, or nx * nouter doubles:
+// sum |psi|^2 of each line's output, at outer * nx + column.
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter, int nblocks,
                           void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream);
 

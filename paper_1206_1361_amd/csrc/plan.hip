@@ -49,6 +49,10 @@ struct gp_plan {
     AxisTables ax[3];
     int xt_y, xt_z;
     int x_blocks, y_blocks, z_blocks;   // blocks launched per sweep
+    // complex64 with an even nx: y/z threads take column pairs (16-byte rows
+    // per thread) whenever psi is 16-byte aligned
+    bool pairs = false;
+    int xt2_y = 0, xt2_z = 0, y2_blocks = 0, z2_blocks = 0;
 
     unsigned char *d_tables = nullptr;
     size_t tab_off[3];
@@ -317,6 +321,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
     const unsigned char *T = p->d_tables;
     const int nd = p->ndim;
+    const bool pair = p->pairs && reinterpret_cast<uintptr_t>(psi) % 16 == 0;
     double dv = 1.0;
     for (int a = 0; a < nd; ++a) dv *= p->dx[a];
     // the last sweep leaves the norm partials, one per line along its axis
@@ -346,16 +351,17 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         if (e != hipSuccess) break;
         if (nd >= 2) {
             e = timed(p, GP_KERNEL_Y, [&] {
-                return gpssc::launch_strided(prec, real, p->ax[1].chunk, p->xt_y, (int)p->n[2],
-                                             p->y_blocks, psi, yargs, T + p->tab_off[1],
-                                             nd == 2 ? parts : nullptr, p->stream);
+                return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair ? p->xt2_y : p->xt_y, pair ? 2 : 1,
+                                             (int)p->n[2], pair ? p->y2_blocks : p->y_blocks, psi, yargs,
+                                             T + p->tab_off[1], nd == 2 ? parts : nullptr, p->stream);
             });
             if (e != hipSuccess) break;
         }
         if (nd == 3) {
             e = timed(p, GP_KERNEL_Z, [&] {
-                return gpssc::launch_strided(prec, real, p->ax[2].chunk, p->xt_z, (int)p->n[1],
-                                             p->z_blocks, psi, zargs, T + p->tab_off[2], parts, p->stream);
+                return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair ? p->xt2_z : p->xt_z, pair ? 2 : 1,
+                                             (int)p->n[1], pair ? p->z2_blocks : p->z_blocks, psi, zargs,
+                                             T + p->tab_off[2], parts, p->stream);
             });
         }
         if (e != hipSuccess || real) continue;
@@ -596,6 +602,13 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
     p->x_blocks = (int)((grid[1] * grid[2] + xl - 1) / xl);
     p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
     p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
+    p->pairs = dtype == GP_C64 && grid[0] % 2 == 0;
+    if (p->pairs) {
+        p->xt2_y = strided_pair_columns(grid[0], p->ax[1].lanes, p->ax[1].chunk);
+        p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
+        p->y2_blocks = (int)(((grid[0] + 2 * p->xt2_y - 1) / (2 * p->xt2_y)) * grid[2]);
+        p->z2_blocks = (int)(((grid[0] + 2 * p->xt2_z - 1) / (2 * p->xt2_z)) * grid[1]);
+    }
     *out = p;
     return GP_OK;
 }
@@ -850,14 +863,25 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     const char *names[] = {"c128", "c64", "c64/f64", "r64", "r32"};
     const char *geoms[] = {"", " circular", " spherical", " axial"};
     const char *dt = names[(int)p->dtype];
+    // y/z columns per block: with column pairs (16-byte aligned psi), 2 per
+    // thread; otherwise one
+    char cols[2][64];
+    for (int a = 0; a < 2; ++a) {
+        const int xt = a ? p->xt_z : p->xt_y, blocks = a ? p->z_blocks : p->y_blocks;
+        if (p->pairs)
+            std::snprintf(cols[a], sizeof cols[a], "%d cols in pairs, %d blocks", 2 * (a ? p->xt2_z : p->xt2_y),
+                          a ? p->z2_blocks : p->y2_blocks);
+        else
+            std::snprintf(cols[a], sizeof cols[a], "%d cols, %d blocks", xt, blocks);
+    }
     std::snprintf(buf, len,
                   "grid %lldx%lldx%lld %dD%s %s %s | x: chunk %d x 64 lanes, %d stages, correction %d, "
-                  "%d blocks | y: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks | "
-                  "z: chunk %d x %d lanes, %d cols, %d stages, correction %d, %d blocks",
+                  "%d blocks | y: chunk %d x %d lanes, %d stages, correction %d, %s | "
+                  "z: chunk %d x %d lanes, %d stages, correction %d, %s",
                   (long long)p->n[0], (long long)p->n[1], (long long)p->n[2], p->ndim, geoms[p->geom],
                   p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
-                  p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, p->xt_y, nst[1], nzc[1], p->y_blocks,
-                  p->ax[2].chunk, p->ax[2].lanes, p->xt_z, nst[2], nzc[2], p->z_blocks);
+                  p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, nst[1], nzc[1], cols[0],
+                  p->ax[2].chunk, p->ax[2].lanes, nst[2], nzc[2], cols[1]);
     return GP_OK;
 }
 

@@ -44,6 +44,19 @@ __device__ __forceinline__ A kfma(cx<A> coef, A t, A v)
 template <typename A>
 __device__ __forceinline__ A cabs2(A a) { return a * a; }
 
+// Column pairs (y/z sweeps of complex64): each column on its own.
+template <bool REAL, typename A>
+__device__ __forceinline__ cx2<A> kmul(cx<A> coef, cx2<A> v)
+{
+    return cx2<A>{kmul<REAL>(coef, v.p), kmul<REAL>(coef, v.q)};
+}
+
+template <bool REAL, typename A>
+__device__ __forceinline__ cx2<A> kfma(cx<A> coef, cx2<A> t, cx2<A> v)
+{
+    return cx2<A>{kfma<REAL>(coef, t.p, v.p), kfma<REAL>(coef, t.q, v.q)};
+}
+
 // Right-hand side (1 - tau/2 T) psi at one point from its neighbours:
 //   (1 - kappa) u + kappa/2 (lo + hi) = u + kappa w,  w = (lo + hi)/2 - u,
 // with kappa = dt/(2 dx^2) (imaginary time) or i dt/(2 dx^2) (real time).
@@ -65,6 +78,12 @@ __device__ __forceinline__ A cn_rhs(A kap, A lo, A u, A hi)
 #pragma clang fp contract(off)
     static_assert(!REAL, "real values carry imaginary-time states only");
     return fma(kap, fma((A)0.5, lo + hi, -u), u);
+}
+
+template <bool REAL, typename A>
+__device__ __forceinline__ cx2<A> cn_rhs(A kap, cx2<A> lo, cx2<A> u, cx2<A> hi)
+{
+    return cx2<A>{cn_rhs<REAL>(kap, lo.p, u.p, hi.p), cn_rhs<REAL>(kap, lo.q, u.q, hi.q)};
 }
 
 // Passes over one chunk of C points held in registers.  The coefficients

@@ -17,14 +17,40 @@
 
 namespace gpssc {
 
-// One tile: XT neighbouring lines (columns) starting at column `col0`, at
-// outer index `outer` (z for the y sweep, y for the z sweep).
-template <typename S, typename A, int C, bool REAL, bool NORM>
+// Column values of one thread: one column (W = 1) or two neighbouring
+// complex64 columns (W = 2, one 16-byte access per row).
+template <typename S, typename A, int W>
+using col_t = typename std::conditional<W == 2, cx2<A>, value_t<S, A>>::type;
+
+template <typename V, int W, typename S>
+__device__ __forceinline__ V load_cols(const S *at)
+{
+    if constexpr (W == 2) {
+        static_assert(std::is_same<S, float2>::value, "column pairs are complex64");
+        return stream_load_pair(at);
+    } else {
+        return ldv<V>(stream_load(at));
+    }
+}
+
+template <int W, typename S, typename V>
+__device__ __forceinline__ void store_cols(S *at, V v)
+{
+    if constexpr (W == 2)
+        stream_store_pair(at, v);
+    else
+        stream_store(at, stv<S>(v));
+}
+
+// One tile: XT*W neighbouring lines (columns) starting at column `col0`, at
+// outer index `outer` (z for the y sweep, y for the z sweep); thread tx holds
+// columns col0 + W tx .. col0 + W tx + W - 1 (W = 2 needs an even nx).
+template <typename S, typename A, int C, bool REAL, bool NORM, int W>
 __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &a,
                                            const cx<A> *__restrict__ zt, double *__restrict__ partials,
                                            unsigned char *smem_raw, int tile, int col0, int outer)
 {
-    using V = value_t<S, A>;
+    using V = col_t<S, A, W>;
     const int XT = blockDim.x;
     const int P = blockDim.y;
     const int tx = threadIdx.x;
@@ -33,7 +59,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     V *b1 = b0 + P * XT;
     const int me = pc * XT + tx;
 
-    const int i = col0 + tx;
+    const int i = col0 + W * tx;
     const bool act = i < a.nx;
     const int pos0 = pc * C;
     const bool full = act && pos0 + C <= a.n;   // whole chunk inside the line
@@ -42,12 +68,12 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     V u[C];
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) u[c] = ldv<V>(stream_load(base + (int64_t)c * a.stride));
+        for (int c = 0; c < C; ++c) u[c] = load_cols<V, W>(base + (int64_t)c * a.stride);
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             u[c] = V{};
-            if (act && pos0 + c < a.n) u[c] = ldv<V>(stream_load(base + (int64_t)c * a.stride));
+            if (act && pos0 + c < a.n) u[c] = load_cols<V, W>(base + (int64_t)c * a.stride);
         }
     }
 
@@ -107,36 +133,48 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
 
     if (full) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) stream_store(base + (int64_t)c * a.stride, stv<S>(u[c]));
+        for (int c = 0; c < C; ++c) store_cols<W>(base + (int64_t)c * a.stride, u[c]);
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (act && pos0 + c < a.n) stream_store(base + (int64_t)c * a.stride, stv<S>(u[c]));
+            if (act && pos0 + c < a.n) store_cols<W>(base + (int64_t)c * a.stride, u[c]);
     }
 
     if (NORM) {
         // sum |psi|^2 of what was stored (rounded to storage), one partial
         // per line (column): over its chunks in order, so the sum does not
-        // depend on how many columns a block holds
-        double acc = 0.0;
+        // depend on how many columns a block or a thread holds
+        double acc[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             if (act && pos0 + c < a.n) {
                 // rounded term by term (no fused multiply-add), the same for
                 // complex and real storage
 #pragma clang fp contract(off)
-                const S v = stv<S>(u[c]);
-                acc += sre(v) * sre(v) + sim(v) * sim(v);
+                if constexpr (W == 2) {
+                    const float2 v0 = st<float2>(u[c].p), v1 = st<float2>(u[c].q);
+                    acc[0] += sre(v0) * sre(v0) + sim(v0) * sim(v0);
+                    acc[1] += sre(v1) * sre(v1) + sim(v1) * sim(v1);
+                } else {
+                    const S v = stv<S>(u[c]);
+                    acc[0] += sre(v) * sre(v) + sim(v) * sim(v);
+                }
             }
         }
         __syncthreads();  // LDS reuse
         double *red = reinterpret_cast<double *>(smem_raw);
-        red[me] = acc;
+#pragma unroll
+        for (int w = 0; w < W; ++w) red[w * P * XT + me] = acc[w];
         __syncthreads();
         if (pc == 0 && act) {
-            double col = 0.0;
-            for (int q = 0; q < P; ++q) col += red[q * XT + tx];
-            partials[(int64_t)outer * a.nx + i] = col;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                double col = 0.0;
+                for (int q = 0; q < P; ++q) col += red[w * P * XT + q * XT + tx];
+                partials[(int64_t)outer * a.nx + i + w] = col;
+            }
         }
     }
 }
@@ -144,7 +182,7 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
 // Tiles are numbered column-tile fastest; block b solves tiles b, b + G, ...
 // (G = gridDim.x); the plan launches one block per tile.  LDS is reused from
 // one tile to the next.
-template <typename S, typename A, int C, bool REAL, bool NORM>
+template <typename S, typename A, int C, bool REAL, bool NORM, int W>
 __global__ void __launch_bounds__(kMaxBlockYZ)
 calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ zt,
                       double *__restrict__ partials, int ncol_tiles, int ntiles)
@@ -152,8 +190,8 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
     extern __shared__ unsigned char smem_raw[];
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int outer = tile / ncol_tiles;
-        const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x;
-        solve_tile<S, A, C, REAL, NORM>(psi, a, zt, partials, smem_raw, tile, col0, outer);
+        const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
+        solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, tile, col0, outer);
         __syncthreads();  // LDS is free for the next tile
     }
 }
@@ -171,7 +209,7 @@ calclu_strided_batch_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__
     const int si = active[slot];
     const int outer = tile / ncol_tiles;
     const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x;
-    solve_tile<S, A, C, REAL, NORM>(psis[si], args[si].s, args[si].zt,
+    solve_tile<S, A, C, REAL, NORM, 1>(psis[si], args[si].s, args[si].zt,
                                     NORM ? partials + part_off[si] : partials, smem_raw, tile, col0,
                                     outer);
 }
@@ -233,28 +271,31 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lan
     return hipErrorInvalidValue;
 }
 
-template <typename S, typename A, bool REAL>
-static hipError_t launch_t(int chunk, int xt, int nouter, int nblocks, void *psi, const void *args,
-                           const void *zt, double *partials, hipStream_t stream)
+template <typename S, typename A, bool REAL, int W>
+static hipError_t launch_tw(int chunk, int xt, int nouter, int nblocks, void *psi, const void *args,
+                            const void *zt, double *partials, hipStream_t stream)
 {
     const SArgs<A> &a = *static_cast<const SArgs<A> *>(args);
     const int P = a.lanes;
     if (xt * P > kMaxBlockYZ || P > kMaxLanesYZ) return hipErrorInvalidValue;
-    const int ncol = (a.nx + xt - 1) / xt;
+    if (W == 2 && (a.nx % 2 != 0 || a.stride % 2 != 0 || a.outer_stride % 2 != 0 ||
+                   reinterpret_cast<uintptr_t>(psi) % 16 != 0))
+        return hipErrorInvalidValue;
+    const int ncol = (a.nx + xt * W - 1) / (xt * W);
     const int ntiles = ncol * nouter;
     const dim3 grid((unsigned)(nblocks > 0 && nblocks < ntiles ? nblocks : ntiles));
     const dim3 block((unsigned)xt, (unsigned)P);
-    const size_t lds = 2 * (size_t)xt * P * sizeof(cx<A>);
+    const size_t lds = 2 * (size_t)xt * P * sizeof(col_t<S, A, W>);
     S *p = static_cast<S *>(psi);
     const cx<A> *z = static_cast<const cx<A> *>(zt);
-#define GP_S_CASE(CC)                                                                           \
-    case CC:                                                                                    \
-        if (partials)                                                                           \
-            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, true>), grid, block, lds,  \
-                               stream, p, a, z, partials, ncol, ntiles);                        \
-        else                                                                                    \
-            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, false>), grid, block, lds, \
-                               stream, p, a, z, partials, ncol, ntiles);                        \
+#define GP_S_CASE(CC)                                                                              \
+    case CC:                                                                                       \
+        if (partials)                                                                              \
+            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, true, W>), grid, block, lds,  \
+                               stream, p, a, z, partials, ncol, ntiles);                           \
+        else                                                                                       \
+            hipLaunchKernelGGL((calclu_strided_kernel<S, A, CC, REAL, false, W>), grid, block, lds, \
+                               stream, p, a, z, partials, ncol, ntiles);                           \
         break;
     switch (chunk) {
         GP_S_CASE(1) GP_S_CASE(2) GP_S_CASE(4) GP_S_CASE(8) GP_S_CASE(16)
@@ -265,21 +306,34 @@ static hipError_t launch_t(int chunk, int xt, int nouter, int nblocks, void *psi
     return hipGetLastError();
 }
 
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int nouter, int nblocks,
+template <typename S, typename A, bool REAL>
+static hipError_t launch_t(int chunk, int xt, int cols, int nouter, int nblocks, void *psi, const void *args,
+                           const void *zt, double *partials, hipStream_t stream)
+{
+    if (cols == 2) {
+        if constexpr (std::is_same<S, float2>::value && std::is_same<A, float>::value)
+            return launch_tw<S, A, REAL, 2>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
+        return hipErrorInvalidValue;
+    }
+    if (cols != 1) return hipErrorInvalidValue;
+    return launch_tw<S, A, REAL, 1>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
+}
+
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter, int nblocks,
                           void *psi, const void *args, const void *zt, double *partials,
                           hipStream_t stream)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
-#define GP_S_PREC(S, A)                                                                           \
-    return real ? launch_t<S, A, true>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream) \
-                : launch_t<S, A, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
+#define GP_S_PREC(S, A)                                                                                 \
+    return real ? launch_t<S, A, true>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, stream) \
+                : launch_t<S, A, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, stream);
     switch (prec) {
     case PREC_C64: GP_S_PREC(float2, float)
     case PREC_C64_F64: GP_S_PREC(float2, double)
     case PREC_C128: GP_S_PREC(double2, double)
     // real storage: imaginary time only (real time was refused above)
-    case PREC_R64: return launch_t<double, double, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
-    case PREC_R32: return launch_t<float, float, false>(chunk, xt, nouter, nblocks, psi, args, zt, partials, stream);
+    case PREC_R64: return launch_t<double, double, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, stream);
+    case PREC_R32: return launch_t<float, float, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, stream);
     }
 #undef GP_S_PREC
     return hipErrorInvalidValue;

@@ -212,6 +212,33 @@ def test_runs_on_a_side_stream():
     assert np.array_equal(to_host(out), ref)
 
 
+@pytest.mark.parametrize("mode", ["real", "imag"])
+@pytest.mark.parametrize("grid", [(64, 40, 36), (24, 300, 18), (16, 12, 520)], ids=lambda g: "x".join(map(str, g)))
+def test_complex64_column_pairs_equal_single_columns(grid, mode):
+    """With an even nx and a 16-byte-aligned psi, a complex64 y/z thread
+    takes two neighbouring columns (one 16-byte access per row); an 8-byte-
+    aligned view of the same data takes one column per thread.  Every column
+    runs the same arithmetic either way, so the two agree bitwise."""
+    dx, dt, omega, g = (0.25, 0.3, 0.35), 0.004, (1.0, 1.3, 0.8), 40.0
+    psi0 = inputs.random_state(grid, dx, seed=11)
+    n = int(np.prod(grid))
+    store = torch.zeros(n + 1, dtype=torch.complex64, device="cuda")
+    single = store[1:].view(grid[::-1])
+    single.copy_(torch.from_numpy(psi0))
+    paired = torch.from_numpy(psi0).to(torch.complex64).cuda()
+    assert paired.data_ptr() % 16 == 0 and single.data_ptr() % 16 == 8
+    with gp.Plan(grid, dx, dt, *omega, g, mode=mode, dtype="c64") as p:
+        assert "in pairs" in p.describe()
+        p.step(paired, 5)
+        p.step(single, 5)
+        o_paired, o_single = p.observables(paired), p.observables(single)
+    assert torch.equal(paired, single)
+    assert o_paired == o_single
+    ref, oref = oracle_run(input_for("c64", psi0), dx, dt, omega, g, mode, 5)
+    assert rel(to_host(paired), ref) <= TOL["c64"][0]
+    assert abs(o_paired["mu"] - oref["mu"]) <= TOL_OBS_SMALL["c64"] * abs(oref["mu"])
+
+
 # ---------------------------------------------------------------- full sizes
 @pytest.fixture(scope="module")
 def large_initial():

@@ -102,12 +102,19 @@ def test_sweep_shapes(n):
         assert c * l >= n and l <= 64 and (l - 1) * c < n
     with pytest.raises(gp.GPError):
         gp.sweep_shape(2048, 1)
-    # FP32 arithmetic, and real FP64 storage on lines up to 256, cut lines
-    # into at most 32 chunks (of at most 16, resp. 8 points)
-    for dt in ("c64", "r32", "r64"):
-        if n <= (512 if dt != "r64" else 256):
+    # short lines take few, long chunks: at most 8 up to 128 points, 16 up
+    # to 256, the same for every storage; real float32 storage cuts longer
+    # lines into at most 32 chunks of at most 16 points, the 16-byte values
+    # (complex128, complex64 column pairs) into chunks of at most 8 points up
+    # to 384 points
+    for dt in ("c128", "c64", "r32", "r64"):
+        if n <= 512:
             c, l = gp.sweep_shape(n, 1, dt)
-            assert l <= 32 and c * l >= n and c <= (16 if dt != "r64" else 8)
+            assert c * l >= n and (l - 1) * c < n and c <= 16
+            assert l <= (8 if n <= 128 else 16 if n <= 256 else 32 if dt == "r32" else 64)
+            if dt != "r32" and 256 < n <= 384:
+                assert c <= 8
+            assert (c, l) == gp.sweep_shape(n, 2, dt)
 
 
 def dense_cn_rhs_solve(n, tab, psi):
