@@ -170,12 +170,12 @@ hipError_t enqueue_step(gp_batch *b)
         e = gpssc::launch_nu_x_batch(prec, real, c.chunk[0], c.nact, c.nlines, b->d_psis, b->d_xargs,
                                      c.d_active, real ? nullptr : b->d_scales, b->own);
         if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.lanes[1], c.nact, c.ncol_y,
-                                        c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr,
+        e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], c.nact,
+                                        c.ncol_y, c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr,
                                         nullptr, b->own);
         if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, real, c.chunk[2], c.xt_z, c.lanes[2], c.nact, c.ncol_z,
-                                        c.ntiles_z, b->d_psis, b->d_zargs, c.d_active,
+        e = gpssc::launch_strided_batch(prec, real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], c.nact,
+                                        c.ncol_z, c.ntiles_z, b->d_psis, b->d_zargs, c.d_active,
                                         real ? nullptr : b->d_partials, b->d_part_off, b->own);
         if (e != hipSuccess) return e;
         if (!real) {
@@ -243,16 +243,19 @@ hipError_t tune_class(gp_batch *b, Class &c)
         const int lanes = c.lanes[ax];
         const int nouter = (int)(ax == 1 ? c.grid[2] : c.grid[1]);
         int best = ax == 1 ? c.xt_y : c.xt_z;
+        int best_cols = ax == 1 ? c.cols_y : c.cols_z;
         float best_ms = 1e30f;
+        for (int cols = 1; cols <= (c.pairs_ok ? 2 : 1) && e == hipSuccess; ++cols)
         for (int xt : {16, 32, 64}) {
             if (xt * lanes > gpssc::kMaxBlockYZ) continue;
-            if (xt > 16 && xt / 2 >= c.grid[0]) continue;
-            const int ncol = (int)((c.grid[0] + xt - 1) / xt);
+            if (xt > 16 && xt * cols / 2 >= c.grid[0]) continue;
+            const int ncol = (int)((c.grid[0] + xt * cols - 1) / (xt * cols));
             const void *args = ax == 1 ? (const void *)b->d_yargs : (const void *)b->d_zargs;
             double *parts = (ax == 2 && !real) ? b->d_partials : nullptr;
             auto run = [&] {
-                return gpssc::launch_strided_batch(prec, real, c.chunk[ax], xt, lanes, 1, ncol, ncol * nouter,
-                                                   d_ptr, args, d_m0, parts, b->d_part_off, b->own);
+                return gpssc::launch_strided_batch(prec, real, c.chunk[ax], xt, cols, lanes, 1, ncol,
+                                                   ncol * nouter, d_ptr, args, d_m0, parts, b->d_part_off,
+                                                   b->own);
             };
             e = run();  // warm
             if (e != hipSuccess) break;
@@ -265,12 +268,16 @@ hipError_t tune_class(gp_batch *b, Class &c)
             if (e == hipSuccess && ms < best_ms) {
                 best_ms = ms;
                 best = xt;
+                best_cols = cols;
             }
         }
-        if (ax == 1)
+        if (ax == 1) {
             c.xt_y = best;
-        else
+            c.cols_y = best_cols;
+        } else {
             c.xt_z = best;
+            c.cols_z = best_cols;
+        }
     }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
@@ -495,6 +502,19 @@ gp_status gp_batch_set_psi(gp_batch *b, void *const *psi, const int64_t *elems)
         b->s[(size_t)i].psi = psi[i];
         b->h_psis[i] = psi[i];
     }
+    // column pairs need every member's psi 16-byte aligned; a class with a
+    // member that is not goes back to one column per thread
+    for (Class &c : b->cls) {
+        if (c.cols_y == 1 && c.cols_z == 1) continue;
+        bool aligned = true;
+        for (int m : c.members) aligned = aligned && (uintptr_t)psi[m] % 16 == 0;
+        if (aligned) continue;
+        c.cols_y = c.cols_z = 1;
+        c.xt_y = class_columns(c, 1, 1, b->dtype);
+        c.xt_z = class_columns(c, 2, 1, b->dtype);
+        class_tiles(c);
+        b->graph_ok = false;
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_psis, b->h_psis, sizeof(void *) * (size_t)b->n, hipMemcpyHostToDevice, b->own);
     if (e == hipSuccess) e = hipStreamSynchronize(b->own);
@@ -633,9 +653,12 @@ gp_status gp_batch_describe(const gp_batch *b, char *buf, size_t len)
     std::string d = std::to_string(b->n) + " solves, " + std::to_string(b->cls.size()) + " classes";
     for (const Class &c : b->cls) {
         char t[200];
-        std::snprintf(t, sizeof t, " | %lldx%lldx%lld: %zu solves, x chunk %d, y chunk %d x %d (%d cols), z chunk %d x %d (%d cols)",
+        std::snprintf(t, sizeof t,
+                      " | %lldx%lldx%lld: %zu solves, x chunk %d, y chunk %d x %d (%d cols%s), z chunk %d x %d "
+                      "(%d cols%s)",
                       (long long)c.grid[0], (long long)c.grid[1], (long long)c.grid[2], c.members.size(), c.chunk[0],
-                      c.chunk[1], c.lanes[1], c.xt_y, c.chunk[2], c.lanes[2], c.xt_z);
+                      c.chunk[1], c.lanes[1], c.xt_y * c.cols_y, c.cols_y == 2 ? " in pairs" : "", c.chunk[2],
+                      c.lanes[2], c.xt_z * c.cols_z, c.cols_z == 2 ? " in pairs" : "");
         d += t;
     }
     std::snprintf(buf, len, "%s", d.c_str());

@@ -414,7 +414,9 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
                              hipStream_t stream);
 
 // partials + part_off[i]: solve i's per-line norm partials (NULL: none).
-hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lanes, int nact,
+// cols: columns per thread as in launch_strided (2: every active solve's psi
+// 16-byte aligned, nx even).
+hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int cols, int lanes, int nact,
                                 int ncol, int ntiles, void *const *psis, const void *args,
                                 const int *active, double *partials, const int64_t *part_off,
                                 hipStream_t stream);

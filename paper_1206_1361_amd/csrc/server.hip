@@ -352,11 +352,11 @@ hipError_t enqueue_step(gp_server *S)
         e = gpssc::launch_nu_x_batch(prec, c.real, c.chunk[0], n, c.nlines, S->d_psis, S->d_xargs, c.d_list,
                                      c.real ? nullptr : S->d_scales, S->stream);
         if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[1], c.xt_y, c.lanes[1], n, c.ncol_y, c.ntiles_y,
-                                        S->d_psis, S->d_yargs, c.d_list, nullptr, nullptr, S->stream);
+        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], n, c.ncol_y,
+                                        c.ntiles_y, S->d_psis, S->d_yargs, c.d_list, nullptr, nullptr, S->stream);
         if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[2], c.xt_z, c.lanes[2], n, c.ncol_z, c.ntiles_z,
-                                        S->d_psis, S->d_zargs, c.d_list, c.real ? nullptr : base,
+        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], n, c.ncol_z,
+                                        c.ntiles_z, S->d_psis, S->d_zargs, c.d_list, c.real ? nullptr : base,
                                         S->d_part_off, S->stream);
         if (e != hipSuccess) return e;
         if (!c.real) {

@@ -28,22 +28,33 @@ struct SolveDesc {
 struct ClassShape {
     int64_t grid[3];
     int chunk[3], lanes[3];
-    int xt_y, xt_z;
+    bool pairs_ok;           // complex64 with an even nx: y/z may take column pairs
+    int xt_y, xt_z;          // threads across a y/z block
+    int cols_y, cols_z;      // columns per thread (1, or 2 = pairs)
     int nlines, ncol_y, ntiles_y, ncol_z, ntiles_z, obs_blocks;
 };
 
 inline void class_tiles(ClassShape &c)
 {
     c.nlines = (int)(c.grid[1] * c.grid[2]);
-    c.ncol_y = (int)((c.grid[0] + c.xt_y - 1) / c.xt_y);
+    const int64_t wy = (int64_t)c.xt_y * c.cols_y, wz = (int64_t)c.xt_z * c.cols_z;
+    c.ncol_y = (int)((c.grid[0] + wy - 1) / wy);
     c.ntiles_y = c.ncol_y * (int)c.grid[2];
-    c.ncol_z = (int)((c.grid[0] + c.xt_z - 1) / c.xt_z);
+    c.ncol_z = (int)((c.grid[0] + wz - 1) / wz);
     c.ntiles_z = c.ncol_z * (int)c.grid[1];
     c.obs_blocks = gpssc::obs_num_blocks((int)c.grid[0], (int)c.grid[1]);
 }
 
-// Chunking, lanes and default y/z block widths of a grid (the grid must
-// have passed sweep_shape on every axis).
+// y/z block width of a class axis (1 = y, 2 = z) at `cols` columns per
+// thread.
+inline int class_columns(const ClassShape &c, int ax, int cols, gp_dtype dtype)
+{
+    return cols == 2 ? strided_pair_columns(c.grid[0], c.lanes[ax], c.chunk[ax])
+                     : strided_columns(c.grid[0], c.lanes[ax], c.chunk[ax], dtype);
+}
+
+// Chunking, lanes and default y/z block shapes of a grid (the grid must
+// have passed sweep_shape on every axis): column pairs where allowed.
 inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
 {
     ClassShape c;
@@ -51,8 +62,10 @@ inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
         c.grid[a] = grid[a];
         sweep_shape(grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype, grid[a]));
     }
-    c.xt_y = strided_columns(c.grid[0], c.lanes[1], c.chunk[1], dtype);
-    c.xt_z = strided_columns(c.grid[0], c.lanes[2], c.chunk[2], dtype);
+    c.pairs_ok = dtype == GP_C64 && grid[0] % 2 == 0;
+    c.cols_y = c.cols_z = c.pairs_ok ? 2 : 1;
+    c.xt_y = class_columns(c, 1, c.cols_y, dtype);
+    c.xt_z = class_columns(c, 2, c.cols_z, dtype);
     class_tiles(c);
     return c;
 }

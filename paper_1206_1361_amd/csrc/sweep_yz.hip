@@ -197,7 +197,9 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
 }
 
 // Batched: block b solves tile b % ntiles of solve active[b / ntiles].
-template <typename S, typename A, int C, bool REAL, bool NORM>
+// With W = 2 (complex64 column pairs) every solve's psi must be 16-byte
+// aligned and its nx even; the host checks both.
+template <typename S, typename A, int C, bool REAL, bool NORM, int W>
 __global__ void __launch_bounds__(kMaxBlockYZ)
 calclu_strided_batch_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__restrict__ args,
                             const int *__restrict__ active, int ncol_tiles, int ntiles,
@@ -208,31 +210,31 @@ calclu_strided_batch_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__
     const int tile = blockIdx.x - slot * ntiles;
     const int si = active[slot];
     const int outer = tile / ncol_tiles;
-    const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x;
-    solve_tile<S, A, C, REAL, NORM, 1>(psis[si], args[si].s, args[si].zt,
-                                    NORM ? partials + part_off[si] : partials, smem_raw, tile, col0,
-                                    outer);
+    const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
+    solve_tile<S, A, C, REAL, NORM, W>(psis[si], args[si].s, args[si].zt,
+                                       NORM ? partials + part_off[si] : partials, smem_raw, tile, col0,
+                                       outer);
 }
 
-template <typename S, typename A, bool REAL>
-static hipError_t launch_batch_t(int chunk, int xt, int lanes, int nact, int ncol, int ntiles,
-                                 void *const *psis, const void *args, const int *active,
-                                 double *partials, const int64_t *part_off, hipStream_t stream)
+template <typename S, typename A, bool REAL, int W>
+static hipError_t launch_batch_tw(int chunk, int xt, int lanes, int nact, int ncol, int ntiles,
+                                  void *const *psis, const void *args, const int *active,
+                                  double *partials, const int64_t *part_off, hipStream_t stream)
 {
     if (xt * lanes > kMaxBlockYZ || lanes > kMaxLanesYZ) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((int64_t)nact * ntiles));
     const dim3 block((unsigned)xt, (unsigned)lanes);
-    const size_t lds = 2 * (size_t)xt * lanes * sizeof(cx<A>);
+    const size_t lds = 2 * (size_t)xt * lanes * sizeof(col_t<S, A, W>);
     S *const *p = reinterpret_cast<S *const *>(psis);
     const SBatchArgs<A> *a = static_cast<const SBatchArgs<A> *>(args);
-#define GP_SB_CASE(CC)                                                                                 \
-    case CC:                                                                                           \
-        if (partials)                                                                                  \
-            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, true>), grid, block, lds,   \
-                               stream, p, a, active, ncol, ntiles, partials, part_off);                \
-        else                                                                                           \
-            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, false>), grid, block, lds,  \
-                               stream, p, a, active, ncol, ntiles, partials, part_off);                \
+#define GP_SB_CASE(CC)                                                                                    \
+    case CC:                                                                                              \
+        if (partials)                                                                                     \
+            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, true, W>), grid, block, lds,   \
+                               stream, p, a, active, ncol, ntiles, partials, part_off);                   \
+        else                                                                                              \
+            hipLaunchKernelGGL((calclu_strided_batch_kernel<S, A, CC, REAL, false, W>), grid, block, lds,  \
+                               stream, p, a, active, ncol, ntiles, partials, part_off);                   \
         break;
     switch (chunk) {
         GP_SB_CASE(1) GP_SB_CASE(2) GP_SB_CASE(4) GP_SB_CASE(8) GP_SB_CASE(16)
@@ -243,17 +245,33 @@ static hipError_t launch_batch_t(int chunk, int xt, int lanes, int nact, int nco
     return hipGetLastError();
 }
 
-hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lanes, int nact,
+template <typename S, typename A, bool REAL>
+static hipError_t launch_batch_t(int chunk, int xt, int cols, int lanes, int nact, int ncol, int ntiles,
+                                 void *const *psis, const void *args, const int *active,
+                                 double *partials, const int64_t *part_off, hipStream_t stream)
+{
+    if (cols == 2) {
+        if constexpr (std::is_same<S, float2>::value && std::is_same<A, float>::value)
+            return launch_batch_tw<S, A, REAL, 2>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active,
+                                                  partials, part_off, stream);
+        return hipErrorInvalidValue;
+    }
+    if (cols != 1) return hipErrorInvalidValue;
+    return launch_batch_tw<S, A, REAL, 1>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, partials,
+                                          part_off, stream);
+}
+
+hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int cols, int lanes, int nact,
                                 int ncol, int ntiles, void *const *psis, const void *args,
                                 const int *active, double *partials, const int64_t *part_off,
                                 hipStream_t stream)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
     if (nact <= 0) return hipSuccess;
-#define GP_SB_PREC(S, A)                                                                              \
-    return real ? launch_batch_t<S, A, true>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, \
-                                             partials, part_off, stream)                              \
-                : launch_batch_t<S, A, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active, \
+#define GP_SB_PREC(S, A)                                                                                    \
+    return real ? launch_batch_t<S, A, true>(chunk, xt, cols, lanes, nact, ncol, ntiles, psis, args, active, \
+                                             partials, part_off, stream)                                    \
+                : launch_batch_t<S, A, false>(chunk, xt, cols, lanes, nact, ncol, ntiles, psis, args, active, \
                                               partials, part_off, stream);
     switch (prec) {
     case PREC_C64: GP_SB_PREC(float2, float)
@@ -261,11 +279,11 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int lan
     case PREC_C128: GP_SB_PREC(double2, double)
     // real storage: imaginary time only (real time was refused above)
     case PREC_R64:
-        return launch_batch_t<double, double, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active,
-                                                     partials, part_off, stream);
+        return launch_batch_t<double, double, false>(chunk, xt, cols, lanes, nact, ncol, ntiles, psis, args,
+                                                     active, partials, part_off, stream);
     case PREC_R32:
-        return launch_batch_t<float, float, false>(chunk, xt, lanes, nact, ncol, ntiles, psis, args, active,
-                                                   partials, part_off, stream);
+        return launch_batch_t<float, float, false>(chunk, xt, cols, lanes, nact, ncol, ntiles, psis, args,
+                                                   active, partials, part_off, stream);
     }
 #undef GP_SB_PREC
     return hipErrorInvalidValue;

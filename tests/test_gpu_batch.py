@@ -71,6 +71,34 @@ def test_batch_matches_single_plans_bitwise(mode, dtype, graph):
             assert obs[i][k] == robs[k], (i, k)
 
 
+@pytest.mark.parametrize("tune", [False, True])
+def test_complex64_column_pairs_and_their_fallback(tune):
+    """complex64 classes with an even nx take column pairs in y and z; a class
+    with a member whose psi is only 8-byte aligned falls back to one column
+    per thread.  Neither enters the rounding: bitwise the single plans."""
+    specs = specs_mixed(5)
+    psi0 = [initial(sp, 30 + i, "c64") for i, sp in enumerate(specs)]
+    psis = [t.clone() for t in psi0]
+    # member 3 (48x40x32) in an 8-byte-aligned view
+    n3 = psis[3].numel()
+    store = torch.zeros(n3 + 1, dtype=torch.complex64, device="cuda")
+    psis[3] = store[1:].view(psis[3].shape)
+    psis[3].copy_(psi0[3])
+    with gp.Batch(specs, mode="imag", dtype="c64", graph=True, tune=tune) as b:
+        before = b.describe()
+        b.bind(psis)
+        after = b.describe()
+        b.step(6)
+        obs = b.observables()
+    if not tune:   # the tuner may prefer one column per thread
+        assert "in pairs" in before.split("24x20x16")[1].split("|")[0]
+    assert "in pairs" not in after.split("48x40x32")[1].split("|")[0]
+    for i, sp in enumerate(specs):
+        ref, robs = run_single(sp, psi0[i], "imag", "c64", 6)
+        assert torch.equal(psis[i], ref), i
+        assert obs[i]["mu"] == robs["mu"], i
+
+
 def test_batch_matches_oracle():
     specs = specs_mixed(2, n=4)
     psi0 = [initial(sp, 20 + i, "c128") for i, sp in enumerate(specs)]
