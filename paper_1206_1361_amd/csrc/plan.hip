@@ -49,9 +49,9 @@ struct gp_plan {
     AxisTables ax[3];
     int xt_y, xt_z;
     int x_blocks, y_blocks, z_blocks;   // blocks launched per sweep
-    // complex64 with an even nx: y/z threads take column pairs (16-byte rows
-    // per thread) whenever psi is 16-byte aligned
-    bool pairs = false;
+    // complex64 with an even nx and long lines: the y/z threads take column
+    // pairs (16-byte rows per thread) whenever psi is 16-byte aligned
+    bool pairs_y = false, pairs_z = false;
     int xt2_y = 0, xt2_z = 0, y2_blocks = 0, z2_blocks = 0;
 
     unsigned char *d_tables = nullptr;
@@ -321,7 +321,8 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     const void *zargs = a32 ? (const void *)&p->sf[1] : (const void *)&p->sd[1];
     const unsigned char *T = p->d_tables;
     const int nd = p->ndim;
-    const bool pair = p->pairs && reinterpret_cast<uintptr_t>(psi) % 16 == 0;
+    const bool aligned16 = reinterpret_cast<uintptr_t>(psi) % 16 == 0;
+    const bool pair_y = p->pairs_y && aligned16, pair_z = p->pairs_z && aligned16;
     double dv = 1.0;
     for (int a = 0; a < nd; ++a) dv *= p->dx[a];
     // the last sweep leaves the norm partials, one per line along its axis
@@ -351,16 +352,18 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         if (e != hipSuccess) break;
         if (nd >= 2) {
             e = timed(p, GP_KERNEL_Y, [&] {
-                return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair ? p->xt2_y : p->xt_y, pair ? 2 : 1,
-                                             (int)p->n[2], pair ? p->y2_blocks : p->y_blocks, psi, yargs,
+                return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair_y ? p->xt2_y : p->xt_y,
+                                             pair_y ? 2 : 1, (int)p->n[2], pair_y ? p->y2_blocks : p->y_blocks,
+                                             psi, yargs,
                                              T + p->tab_off[1], nd == 2 ? parts : nullptr, p->stream);
             });
             if (e != hipSuccess) break;
         }
         if (nd == 3) {
             e = timed(p, GP_KERNEL_Z, [&] {
-                return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair ? p->xt2_z : p->xt_z, pair ? 2 : 1,
-                                             (int)p->n[1], pair ? p->z2_blocks : p->z_blocks, psi, zargs,
+                return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
+                                             pair_z ? 2 : 1, (int)p->n[1], pair_z ? p->z2_blocks : p->z_blocks,
+                                             psi, zargs,
                                              T + p->tab_off[2], parts, p->stream);
             });
         }
@@ -602,11 +605,14 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
     p->x_blocks = (int)((grid[1] * grid[2] + xl - 1) / xl);
     p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
     p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
-    p->pairs = dtype == GP_C64 && grid[0] % 2 == 0;
-    if (p->pairs) {
+    p->pairs_y = pair_axis(dtype, grid, 1);
+    p->pairs_z = pair_axis(dtype, grid, 2);
+    if (p->pairs_y) {
         p->xt2_y = strided_pair_columns(grid[0], p->ax[1].lanes, p->ax[1].chunk);
-        p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
         p->y2_blocks = (int)(((grid[0] + 2 * p->xt2_y - 1) / (2 * p->xt2_y)) * grid[2]);
+    }
+    if (p->pairs_z) {
+        p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
         p->z2_blocks = (int)(((grid[0] + 2 * p->xt2_z - 1) / (2 * p->xt2_z)) * grid[1]);
     }
     *out = p;
@@ -868,7 +874,7 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     char cols[2][64];
     for (int a = 0; a < 2; ++a) {
         const int xt = a ? p->xt_z : p->xt_y, blocks = a ? p->z_blocks : p->y_blocks;
-        if (p->pairs)
+        if (a ? p->pairs_z : p->pairs_y)
             std::snprintf(cols[a], sizeof cols[a], "%d cols in pairs, %d blocks", 2 * (a ? p->xt2_z : p->xt2_y),
                           a ? p->z2_blocks : p->y2_blocks);
         else

@@ -54,7 +54,7 @@ inline int class_columns(const ClassShape &c, int ax, int cols, gp_dtype dtype)
 }
 
 // Chunking, lanes and default y/z block shapes of a grid (the grid must
-// have passed sweep_shape on every axis): column pairs where allowed.
+// have passed sweep_shape on every axis): column pairs as pair_axis says.
 inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
 {
     ClassShape c;
@@ -63,7 +63,8 @@ inline ClassShape class_shape(const int64_t grid[3], gp_dtype dtype)
         sweep_shape(grid[a], a, &c.chunk[a], &c.lanes[a], max_lanes_for(dtype, grid[a]));
     }
     c.pairs_ok = dtype == GP_C64 && grid[0] % 2 == 0;
-    c.cols_y = c.cols_z = c.pairs_ok ? 2 : 1;
+    c.cols_y = pair_axis(dtype, grid, 1) ? 2 : 1;
+    c.cols_z = pair_axis(dtype, grid, 2) ? 2 : 1;
     c.xt_y = class_columns(c, 1, c.cols_y, dtype);
     c.xt_z = class_columns(c, 2, c.cols_z, dtype);
     class_tiles(c);

@@ -76,10 +76,12 @@ def test_complex64_column_pairs_and_their_fallback(tune):
     """complex64 classes with an even nx take column pairs in y and z; a class
     with a member whose psi is only 8-byte aligned falls back to one column
     per thread.  Neither enters the rounding: bitwise the single plans."""
-    specs = specs_mixed(5)
+    # z lines of 272 points take pairs by default; y lines of 20 do not
+    grids = [(24, 20, 272), (18, 16, 272), (24, 20, 272), (18, 16, 272), (33, 17, 9)]
+    specs = [dict(sp, grid=g) for sp, g in zip(specs_mixed(5, len(grids)), grids)]
     psi0 = [initial(sp, 30 + i, "c64") for i, sp in enumerate(specs)]
     psis = [t.clone() for t in psi0]
-    # member 3 (48x40x32) in an 8-byte-aligned view
+    # member 3 (18x16x272) in an 8-byte-aligned view
     n3 = psis[3].numel()
     store = torch.zeros(n3 + 1, dtype=torch.complex64, device="cuda")
     psis[3] = store[1:].view(psis[3].shape)
@@ -91,8 +93,9 @@ def test_complex64_column_pairs_and_their_fallback(tune):
         b.step(6)
         obs = b.observables()
     if not tune:   # the tuner may prefer one column per thread
-        assert "in pairs" in before.split("24x20x16")[1].split("|")[0]
-    assert "in pairs" not in after.split("48x40x32")[1].split("|")[0]
+        assert "in pairs" in before.split("24x20x272")[1].split("|")[0]
+        assert "in pairs" in after.split("24x20x272")[1].split("|")[0]
+    assert "in pairs" not in after.split("18x16x272")[1].split("|")[0]
     for i, sp in enumerate(specs):
         ref, robs = run_single(sp, psi0[i], "imag", "c64", 6)
         assert torch.equal(psis[i], ref), i

@@ -213,12 +213,13 @@ def test_runs_on_a_side_stream():
 
 
 @pytest.mark.parametrize("mode", ["real", "imag"])
-@pytest.mark.parametrize("grid", [(64, 40, 36), (24, 300, 18), (16, 12, 520)], ids=lambda g: "x".join(map(str, g)))
+@pytest.mark.parametrize("grid", [(24, 300, 18), (16, 12, 520), (34, 264, 260)], ids=lambda g: "x".join(map(str, g)))
 def test_complex64_column_pairs_equal_single_columns(grid, mode):
-    """With an even nx and a 16-byte-aligned psi, a complex64 y/z thread
-    takes two neighbouring columns (one 16-byte access per row); an 8-byte-
-    aligned view of the same data takes one column per thread.  Every column
-    runs the same arithmetic either way, so the two agree bitwise."""
+    """With an even nx, lines of more than 256 points and a 16-byte-aligned
+    psi, a complex64 y/z thread takes two neighbouring columns (one 16-byte
+    access per row); an 8-byte-aligned view of the same data takes one column
+    per thread.  Every column runs the same arithmetic either way, so the two
+    agree bitwise."""
     dx, dt, omega, g = (0.25, 0.3, 0.35), 0.004, (1.0, 1.3, 0.8), 40.0
     psi0 = inputs.random_state(grid, dx, seed=11)
     n = int(np.prod(grid))
