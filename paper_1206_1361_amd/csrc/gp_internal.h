@@ -139,20 +139,20 @@ __device__ __forceinline__ double sim(S v)
         return 0.0;
 }
 
-// v * s componentwise: the product formed in FP64 and rounded once to the
-// storage type.  (Rounding s to float first would move every element of a
-// float state by the same relative amount, up to 2^-24, and the norm by
-// twice that.)
+// v * s componentwise in the storage precision (s rounded to it).  For a
+// float state this leaves the norm within about one float ulp of 1: a factor
+// that close to 1 rounds most elements back to themselves.  That is also what
+// lets a converged float state become an exact fixed point of the step, which
+// the imaginary-time stopping rule relies on.
 template <typename S>
-__device__ __forceinline__ S sscale(S v, double s)
+__device__ __forceinline__ S sscale(S v, typename storage_traits<S>::real s)
 {
-    using R = typename storage_traits<S>::real;
     if constexpr (storage_traits<S>::complex) {
-        v.x = (R)((double)v.x * s);
-        v.y = (R)((double)v.y * s);
+        v.x *= s;
+        v.y *= s;
         return v;
     } else {
-        return (R)((double)v * s);
+        return v * s;
     }
 }
 

@@ -80,8 +80,9 @@ __global__ void __launch_bounds__(kReduceThreads)
 scale_batch_kernel(S *const *__restrict__ psis, const int *__restrict__ active, int64_t elems,
                    const double *__restrict__ scales)
 {
+    using R = typename storage_traits<S>::real;
     const int si = active[blockIdx.y];
-    const double s = scales[si];
+    const R s = (R)scales[si];
     S *psi = psis[si];
     const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
     for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
@@ -99,7 +100,8 @@ template <typename S>
 __global__ void __launch_bounds__(kReduceThreads)
 scale_kernel(S *__restrict__ psi, int64_t elems, const double *__restrict__ scale)
 {
-    const double s = *scale;
+    using R = typename storage_traits<S>::real;
+    const R s = (R)(*scale);
     const int64_t stride = (int64_t)gridDim.x * kReduceThreads;
     for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems; p += stride) {
         psi[p] = sscale(psi[p], s);

@@ -100,11 +100,14 @@ def test_steps_match_oracle(grid, mode, dtype):
 
 # Per-observable bounds on the small imaginary-time workload.  mu and E are
 # stationary at the ground state, so the FP32 rounding of psi enters them at
-# second order; the norm is restored every step; the rms sizes are linear in
-# the psi error, whose FP32 level is a few 2^-24, hence 1e-6.
+# second order; the rms sizes are linear in the psi error, whose FP32 level is
+# a few 2^-24, hence 1e-6.  The norm is restored every step, but a float state
+# can only be brought to within about one float ulp of norm 1: multiplying by
+# a factor that close to 1 rounds most elements back to themselves, so the
+# norm stays off by up to 2 * 2^-24 = 1.2e-7; hence 2e-7.
 OBS_TOL_SMALL_IMAG = {
     "c128": {k: 1e-12 for k in ("mu", "energy", "norm", "rms_x", "rms_y", "rms_z", "rms_r")},
-    "c64": {"mu": 1e-7, "energy": 1e-7, "norm": 1e-7,
+    "c64": {"mu": 1e-7, "energy": 1e-7, "norm": 2e-7,
             "rms_x": 1e-6, "rms_y": 1e-6, "rms_z": 1e-6, "rms_r": 1e-6},
 }
 OBS_TOL_SMALL_IMAG["c64_f64"] = OBS_TOL_SMALL_IMAG["c64"]
