@@ -76,6 +76,10 @@ def input_for(dtype, psi):
 SMALL_GRIDS = [
     (1, 1, 1), (5, 1, 1), (1, 6, 1), (1, 1, 7), (7, 5, 3), (33, 17, 9), (64, 64, 64),
     (65, 70, 66), (130, 63, 97), (200, 129, 40),
+    # enough x lines for a wavefront to interleave several: 4 lines of 2-point
+    # chunks (16384 lines), 4 of 1-point chunks with a ragged last group
+    # (16510 lines), 2 of 4-point chunks (9216 lines)
+    (100, 128, 128), (33, 130, 127), (200, 96, 96),
 ]
 
 
@@ -111,6 +115,17 @@ OBS_TOL_SMALL_IMAG = {
             "rms_x": 1e-6, "rms_y": 1e-6, "rms_z": 1e-6, "rms_r": 1e-6},
 }
 OBS_TOL_SMALL_IMAG["c64_f64"] = OBS_TOL_SMALL_IMAG["c64"]
+
+
+@pytest.mark.parametrize("grid,lines_per_wave", [((100, 128, 128), 4), ((33, 130, 127), 4),
+                                                  ((200, 96, 96), 2), ((64, 64, 64), 1), ((512, 40, 30), 1)])
+def test_x_lines_per_wavefront(grid, lines_per_wave):
+    """A wavefront interleaves up to 4 lines of 1-2-point chunks or 2 of 3-4,
+    while at least 4096 wavefronts remain; the x launch shows it."""
+    with gp.Plan(grid, (0.3,) * 3, 0.01, 1, 1, 1, 1.0, mode="imag") as p:
+        blocks = int(p.describe().split("| x:")[1].split("blocks")[0].split(",")[-1])
+    lines = grid[1] * grid[2]
+    assert blocks == -(-lines // lines_per_wave)
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

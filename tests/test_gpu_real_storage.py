@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 import paper_1206_1361_amd as gp  # noqa: E402
 
 PAIRS = {"r64": ("c128", torch.float64, torch.complex128), "r32": ("c64", torch.float32, torch.complex64)}
-GRIDS = [(24, 20, 16), (33, 17, 9), (65, 40, 31), (1, 1, 1), (7, 1, 5)]
+GRIDS = [(24, 20, 16), (33, 17, 9), (65, 40, 31), (1, 1, 1), (7, 1, 5), (100, 128, 128)]
 
 
 def state(grid, dx, trap, seed):
