@@ -71,6 +71,24 @@ def test_batch_matches_single_plans_bitwise(mode, dtype, graph):
             assert obs[i][k] == robs[k], (i, k)
 
 
+@pytest.mark.parametrize("mode", ["real", "imag"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_interleaved_x_lines_across_solves(dtype, mode):
+    """Three solves of 6111 x lines each: the batch's x launch interleaves 4
+    lines per wavefront, with groups that straddle two solves and a ragged
+    last group; a single plan of 6111 lines solves one line per wavefront.
+    The lines' arithmetic does not depend on that: bitwise equal."""
+    specs = [dict(sp, grid=(40, 63, 97)) for sp in specs_mixed(7, 3)]
+    psi0 = [initial(sp, 50 + i, dtype) for i, sp in enumerate(specs)]
+    psis = [t.clone() for t in psi0]
+    with gp.Batch(specs, mode=mode, dtype=dtype, graph=False) as b:
+        b.bind(psis)
+        b.step(3)
+    for i, sp in enumerate(specs):
+        ref, _ = run_single(sp, psi0[i], mode, dtype, 3)
+        assert torch.equal(psis[i], ref), i
+
+
 @pytest.mark.parametrize("tune", [False, True])
 def test_complex64_column_pairs_and_their_fallback(tune):
     """complex64 classes with an even nx take column pairs in y and z; a class
