@@ -111,7 +111,6 @@ __device__ __forceinline__ void solve_x_line(S (&row_vals)[C], S *buf, const XAr
 // them in one instruction stream so that their loads, shuffles and LDS
 // round trips overlap, and every line sees exactly the arithmetic of a line
 // solved alone.
-// args_of(l): the XArgs of line l's grid (sizes, trap, coefficients).
 template <typename A>
 struct XLine {
     const cx<A> *zt;           // boundary correction of the line's grid
@@ -119,6 +118,8 @@ struct XLine {
     int line;                  // j + ny k
 };
 
+// args_of(l): the XArgs of line l's grid (sizes, trap, coefficients);
+// ln(l): its XLine.
 template <typename S, typename A, int C, int L, bool REAL, typename ArgsOf, typename LineOf>
 __device__ __forceinline__ void solve_x_lines(S (&rows)[L][C], S *buf, ArgsOf args_of, LineOf ln)
 {
