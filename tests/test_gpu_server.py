@@ -98,6 +98,22 @@ def test_served_results_equal_single_plans(dtype):
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
 
 
+def test_long_lines_served_with_column_pairs_equal_single_plans():
+    """complex64 z lines of 272 points take column pairs, in the server's
+    batched kernels as in a single plan: the results agree bitwise."""
+    rqs = [dict(rq, psi=inputs.gaussian((16, 12, 272), (rq["dx"],) * 3, rq["trap"]).astype(np.complex64))
+           for rq in requests(6, n=3)]
+    with gp.Server(dtype="c64", hbm_budget=256 << 20, max_slots=8, check_every=K) as srv:
+        for i, rq in enumerate(rqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(rqs))
+    for i, rq in enumerate(rqs):
+        ref, robs, steps, conv = plan_reference(rq, "c64")
+        assert got[i]["status"] == 0 and got[i]["steps"] == steps, i
+        assert np.array_equal(got[i]["psi"], ref), i
+        assert got[i]["obs"]["mu"] == robs["mu"], i
+
+
 def test_same_alone_and_in_the_mix():
     """Each request served alone equals the same request served while others
     arrive, run and leave around it (bitwise)."""
