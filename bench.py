@@ -297,7 +297,7 @@ def main() -> int:
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the step is measured on a single MI355X "
-              "(multi-GPU sharding of one grid is a design, not part of this build).", file=sys.stderr)
+              "(the sharding of one grid over several GPUs is designed, not implemented).", file=sys.stderr)
         return 2
 
     import torch
