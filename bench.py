@@ -21,7 +21,9 @@ runs 256 uneven imaginary-time ground-state solves (grids 48^3 to 160^3,
 dx 0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between
 checks 10 steps apart) as one complex64 batch and, for comparison, one by
 one on complex128 plans, with the complex64 error at equal step counts.
-`serve` drives the request server with Poisson arrivals at 50/s of mixed
+`cache_resident` times the 240x200x160 quench grid, whose state fits the
+Infinity Cache (effective rates, not HBM figures).  `serve` drives the
+request server with Poisson arrivals at 50/s of mixed
 ground-state and real-time requests (64^3 to 160x128x96) for a few seconds
 and reports p50/p99 latency and throughput (python -m
 paper_1206_1361_amd.serve runs the full 60 s).
@@ -118,6 +120,38 @@ def run_dtype(gp, torch, w, psi_host, dtype: str, steps: int, warmup: int) -> di
         "step_hbm_frac": round(step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4),
         "norm_drift": abs(n1 - n0),
     }
+
+
+def cache_resident(gp, torch, steps: int) -> dict:
+    """The 240x200x160 quench grid (after the g 22 -> 11 quench), complex128
+    and complex64.  Its 117 MiB (59 MiB) fit the 256 MB Infinity Cache, so
+    the sweeps' rates are effective ones, not HBM figures."""
+    from paper_1206_1361_amd import inputs
+
+    w = inputs.QUENCH
+    psi_host = inputs.initial_state(w)
+    out = {"workload": w.name, "grid": list(w.grid), "steps": steps,
+           "note": "the state fits the 256 MB Infinity Cache: effective rates, not HBM bandwidth"}
+    for dtype in ("c128", "c64"):
+        psi = torch.from_numpy(psi_host).to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+        bpp = 16 if dtype == "c128" else 8
+        with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g_after, mode=w.mode, dtype=dtype) as plan:
+            plan.step(psi, 10)
+            plan.sync()
+            plan.profile(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.step(psi, steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            prof = plan.profile_read()
+            plan.profile(False)
+        alg = 2 * w.points * bpp
+        out[dtype] = {"value": w.points * steps / (t1 - t0), "ms_per_step": (t1 - t0) / steps * 1e3,
+                      "effective_GB/s": {k: round(alg / (ms / n * 1e-3) / 1e9, 1)
+                                         for k, (ms, n) in prof.items() if n}}
+        del psi
+    return out
 
 
 def cpu_baseline(w, psi_host, budget_s: float) -> dict:
@@ -282,6 +316,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--latency-repeats", type=int, default=50)
+    ap.add_argument("--cache-steps", type=int, default=200,
+                    help="steps timed on the cache-resident 240x200x160 quench grid (0: skip)")
     ap.add_argument("--only", choices=["c128", "c64", "c64_f64"], default=None,
                     help="run one dtype only (profiling runs)")
     ap.add_argument("--batch-solves", type=int, default=256,
@@ -352,6 +388,9 @@ def main() -> int:
                            "value": q["value"], "ms_per_step": q["ms_per_step"],
                            "roofline": q["roofline"], "kernels": q["kernels"],
                            "step_hbm_frac": q["step_hbm_frac"], "norm_drift": q["norm_drift"]}
+    if args.cache_steps > 0:
+        log("[bench] the cache-resident quench grid")
+        out["cache_resident"] = cache_resident(gp, torch, args.cache_steps)
     if args.latency_repeats > 0:
         log("[bench] latency of the small imaginary-time solve")
         out["latency"] = latency(gp, torch, args.latency_repeats)
