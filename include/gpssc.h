@@ -179,8 +179,11 @@ gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
 /* Queues `nsteps` split-step Crank-Nicolson steps on psi, in place, and
  * returns without waiting.  psi_dev is a device pointer to psi_elems complex
  * numbers of the plan's dtype (psi_elems must equal Nx*Ny*Nz; 16-byte
- * alignment for GP_C128, 8-byte for the complex64 dtypes); the caller owns it, and the
- * library keeps no reference after the work completes.  One step is, in
+ * alignment for GP_C128, 8-byte for the complex64 dtypes, real parts only for
+ * GP_R64 / GP_R32); the caller owns it, and the library keeps no reference
+ * after the work completes.  A GP_C64 psi that is 16-byte aligned lets the
+ * y/z sweeps of lines longer than 256 points take two columns per thread
+ * (same results, faster).  One step is, in
  * order: calcnu (psi <- exp(-tau (V + g|psi|^2)) psi, tau = dt or i dt),
  * calclux, calcluy, calcluz (one Crank-Nicolson solve per grid line along
  * each axis by the precomputed Thomas recursion) and, in imaginary time,
