@@ -369,8 +369,10 @@ hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, 
 // (each loops over tiles; 0 or >= the tile count = one per tile).  zt:
 // boundary correction by position.  partials: NULL, or nx * nouter doubles:
 // sum |psi|^2 of each line's output, at outer * nx + column.
+// xcd_ranges: hand each XCD a contiguous range of tiles (the y sweep; see
+// calclu_strided_kernel).
 hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter, int nblocks,
-                          void *psi, const void *args, const void *zt, double *partials,
+                          void *psi, const void *args, const void *zt, double *partials, bool xcd_ranges,
                           hipStream_t stream);
 
 // calcnorm: sums `n` partials (each times weights[b] when weights is not

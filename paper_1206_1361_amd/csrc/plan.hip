@@ -354,8 +354,8 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
             e = timed(p, GP_KERNEL_Y, [&] {
                 return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair_y ? p->xt2_y : p->xt_y,
                                              pair_y ? 2 : 1, (int)p->n[2], pair_y ? p->y2_blocks : p->y_blocks,
-                                             psi, yargs,
-                                             T + p->tab_off[1], nd == 2 ? parts : nullptr, p->stream);
+                                             psi, yargs, T + p->tab_off[1], nd == 2 ? parts : nullptr,
+                                             true, p->stream);
             });
             if (e != hipSuccess) break;
         }
@@ -363,8 +363,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
             e = timed(p, GP_KERNEL_Z, [&] {
                 return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
                                              pair_z ? 2 : 1, (int)p->n[1], pair_z ? p->z2_blocks : p->z_blocks,
-                                             psi, zargs,
-                                             T + p->tab_off[2], parts, p->stream);
+                                             psi, zargs, T + p->tab_off[2], parts, false, p->stream);
             });
         }
         if (e != hipSuccess || real) continue;
