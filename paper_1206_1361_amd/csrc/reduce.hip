@@ -28,21 +28,38 @@ __device__ double block_sum(double v, double *red)
     return r;
 }
 
+// Thread t's share of a norm sum: p[b] (times w[b], the product rounded on
+// its own) added for b = t, t + kReduceThreads, ... in that order.  The loads
+// of kSumAhead terms are issued before they are added, so the thread does
+// not wait on each load in turn; the order of the additions is unchanged.
+constexpr int kSumAhead = 8;
+
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, const double *__restrict__ w, int n,
+                                              int t)
+{
+#pragma clang fp contract(off)
+    double acc = 0.0;
+    for (int b0 = t; b0 < n; b0 += kSumAhead * kReduceThreads) {
+        double v[kSumAhead];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            const int b = b0 + u * kReduceThreads;
+            v[u] = b < n ? (w ? w[b] * p[b] : p[b]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u)
+            if (b0 + u * kReduceThreads < n) acc += v[u];
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 calcnorm_finalize_kernel(const double *__restrict__ partials, int n, double dv,
                          double *__restrict__ scale, int *__restrict__ flag,
                          const double *__restrict__ weights)
 {
     __shared__ double red[kReduceThreads];
-    double acc = 0.0;
-    if (weights) {
-        for (int b = threadIdx.x; b < n; b += kReduceThreads) {
-#pragma clang fp contract(off)
-            acc += weights[b] * partials[b];
-        }
-    } else {
-        for (int b = threadIdx.x; b < n; b += kReduceThreads) acc += partials[b];
-    }
+    const double acc = strided_sum(partials, weights, n, threadIdx.x);
     const double sum = block_sum(acc, red);
     if (threadIdx.x == 0) {
         const double norm = dv * sum;
@@ -61,9 +78,7 @@ calcnorm_finalize_batch_kernel(const int *__restrict__ active, const double *__r
 {
     __shared__ double red[kReduceThreads];
     const int si = active[blockIdx.x];
-    const double *p = partials + part_off[si];
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < ntiles; b += kReduceThreads) acc += p[b];
+    const double acc = strided_sum(partials + part_off[si], nullptr, ntiles, threadIdx.x);
     const double sum = block_sum(acc, red);
     if (threadIdx.x == 0) {
         const double norm = dv[si] * sum;
