@@ -155,8 +155,11 @@ struct AxisTables {
 // The factorisation: c is the root of o c^2 - b c + o = 0 inside the unit
 // circle (the two roots multiply to 1), taken as 2o / (b + sqrt(b^2 - 4o^2))
 // with the square root that makes |c| < 1, so nothing cancels.  beta = o/c,
-// so beta (1 + c^2) = b and beta c = o.
-inline void build_axis(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t)
+// so beta (1 + c^2) = b and beta c = o.  Fills t's coefficients and the
+// boundary correction zt[0..n) into caller-provided arrays (w and z: n
+// entries of work space each), allocating nothing.
+inline void build_axis_into(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t,
+                            cplx *zt, cplx *w, cplx *z)
 {
     const cplx tau = real ? cplx(0.0, dt) : cplx(dt, 0.0);
     t.n = n;
@@ -173,22 +176,28 @@ inline void build_axis(int64_t n, double dx, double dt, bool real, int chunk, in
     t.a = -t.c;
     // z = M^-1 e_0 for M = beta (I + c S)(I + c S^T): forward w_i = a^i / beta,
     // then back substitution y_i = w_i + a y_{i+1} from the last node.
-    std::vector<cplx> w((size_t)n), z((size_t)n);
     w[0] = t.m;
-    for (int64_t i = 1; i < n; ++i) w[(size_t)i] = t.a * w[(size_t)i - 1];
-    z[(size_t)n - 1] = w[(size_t)n - 1];
-    for (int64_t i = n - 2; i >= 0; --i) z[(size_t)i] = w[(size_t)i] + t.a * z[(size_t)i + 1];
+    for (int64_t i = 1; i < n; ++i) w[i] = t.a * w[i - 1];
+    z[n - 1] = w[n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) z[i] = w[i] + t.a * z[i + 1];
     // A = M + u e_0^T, u = beta c^2 e_0:  x = y - (beta c^2 y_0 / (1 + beta c^2 z_0)) z
     const cplx bc2 = t.beta * t.c * t.c;
     const cplx gam = -bc2 / (1.0 + bc2 * z[0]);
-    t.zt.resize((size_t)n);
-    for (int64_t i = 0; i < n; ++i) t.zt[(size_t)i] = gam * z[(size_t)i];
+    for (int64_t i = 0; i < n; ++i) zt[i] = gam * z[i];
     cplx p(1.0, 0.0);
     for (int q = 0; q < chunk; ++q) p *= t.a;
     for (int s = 0; s < gpssc::kMaxStages; ++s) {
         t.stage[s] = p;
         p *= p;
     }
+}
+
+// build_axis_into with the correction kept in t.zt.
+inline void build_axis(int64_t n, double dx, double dt, bool real, int chunk, int lanes, AxisTables &t)
+{
+    std::vector<cplx> w((size_t)n), z((size_t)n);
+    t.zt.resize((size_t)n);
+    build_axis_into(n, dx, dt, real, chunk, lanes, t, t.zt.data(), w.data(), z.data());
 }
 
 template <typename A>
@@ -203,7 +212,7 @@ inline bool is_zero(cplx v) { return (A)v.real() == (A)0 && (A)v.imag() == (A)0;
 // because no lane has a partner there.  The correction is kept up to its last
 // position that does not round to zero.
 template <typename A>
-inline gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, double dt, double dx)
+inline gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, const cplx *zt, double dt, double dx)
 {
     gpssc::SweepCoef<A> k;
     k.kap = (A)(dt / (2.0 * dx * dx));
@@ -215,9 +224,15 @@ inline gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, double dt, double dx)
         if ((1 << s) < t.lanes && !is_zero<A>(t.stage[s]) && k.nst == s) k.nst = s + 1;
     }
     int nz = (int)t.n;
-    while (nz > 0 && is_zero<A>(t.zt[(size_t)nz - 1])) --nz;
+    while (nz > 0 && is_zero<A>(zt[nz - 1])) --nz;
     k.nzc = nz;
     return k;
+}
+
+template <typename A>
+inline gpssc::SweepCoef<A> sweep_coef(const AxisTables &t, double dt, double dx)
+{
+    return sweep_coef<A>(t, t.zt.data(), dt, dx);
 }
 
 // Device image of the correction vectors of the three axes, in the

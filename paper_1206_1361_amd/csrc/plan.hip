@@ -67,6 +67,7 @@ struct gp_plan {
     int *h_flag = nullptr;      // pinned
 
     int64_t steps_done = 0;
+    hipEvent_t ev_switch = nullptr;   // orders a new stream after the old one (gp_set_stream)
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> pool;
@@ -87,8 +88,10 @@ struct gp_plan {
 
 namespace {
 
+// zt[a]: the boundary correction of axis a (its last nonzero position sets
+// how far the kernels apply it).
 template <typename A>
-void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
+void fill_args(gp_plan *p, const cplx *const zt[3], gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
 {
     x.nx = (int)p->n[0];
     x.ny = (int)p->n[1];
@@ -104,7 +107,7 @@ void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
     x.hgz = (A)(0.5 * p->omega[2] * p->omega[2]);
     x.dt = (A)p->dt;
     x.g = (A)p->g;
-    x.k = sweep_coef<A>(p->ax[0], p->dt, p->dx[0]);
+    x.k = sweep_coef<A>(p->ax[0], zt[0], p->dt, p->dx[0]);
     for (int a = 1; a < 3; ++a) {
         gpssc::SArgs<A> &t = s[a - 1];
         t.nx = (int)p->n[0];
@@ -112,7 +115,7 @@ void fill_args(gp_plan *p, gpssc::XArgs<A> &x, gpssc::SArgs<A> s[2])
         t.lanes = p->ax[a].lanes;
         t.stride = a == 1 ? p->n[0] : p->n[0] * p->n[1];
         t.outer_stride = a == 1 ? p->n[0] * p->n[1] : p->n[0];
-        t.k = sweep_coef<A>(p->ax[a], p->dt, p->dx[a]);
+        t.k = sweep_coef<A>(p->ax[a], zt[a], p->dt, p->dx[a]);
     }
 }
 
@@ -168,6 +171,7 @@ void release(gp_plan *p)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+    if (p->ev_switch) (void)hipEventDestroy(p->ev_switch);
     if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->d_partials) (void)hipFree(p->d_partials);
     if (p->d_obs_partials) (void)hipFree(p->d_obs_partials);
@@ -231,6 +235,59 @@ void radial_tables(int dim, int64_t n, double h, double dt, bool real, int npad,
         tab[4 * (size_t)npad + i] = -l_lo / den;         // a
         tab[5 * (size_t)npad + i] = -cur;                // b
         cprev = cur;
+    }
+}
+
+// Arguments of a plan (gp_plan_create_nd), checked before any device call;
+// on success chunk and lanes hold the chunking of every axis.
+gp_status check_plan_args(int ndim, const int64_t grid[3], const double dx[3], double dt, const double om[3],
+                          double g, gp_mode mode, gp_dtype dtype, int chunk[3], int lanes[3])
+{
+    if (!valid_grid(grid)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
+    if (ndim < 1 || ndim > 3) return fail(GP_ERR_INVALID, "ndim must be 1, 2 or 3");
+    for (int a = ndim; a < 3; ++a)
+        if (grid[a] != 1) return fail(GP_ERR_INVALID, "axes beyond ndim must have one node");
+    if (!dx || !finite_pos(dx[0]) || !finite_pos(dx[1]) || !finite_pos(dx[2]))
+        return fail(GP_ERR_INVALID, "dx must be finite and > 0");
+    if (!finite_pos(dt)) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(om[a]) || om[a] < 0.0)
+            return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+    if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
+    if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
+    if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
+    if (real_storage(dtype) && mode != GP_MODE_IMAG)
+        return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
+    for (int a = 0; a < 3; ++a)
+        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a], max_lanes_for(dtype, grid[a])))
+            return fail(GP_ERR_UNSUPPORTED, "grid line too long (Nx <= 1024, Ny, Nz <= 1024)");
+    if (grid[1] * grid[2] > 0x7fffffffLL || grid[1] > 65535 || grid[2] > 65535)
+        return fail(GP_ERR_UNSUPPORTED, "too many grid lines for one launch");
+    return GP_OK;
+}
+
+// Blocks per sweep and the complex64 column pairs, from the grid, the dtype
+// and the chunking (p->ax, p->xt_y, p->xt_z set).  One block per line (x)
+// or tile (y, z): blocks that finish early make room for the next ones, so
+// the blocks on a compute unit drift out of step and their load, compute and
+// store phases overlap.  (A grid of resident blocks looping over the work
+// keeps them in lockstep and was measured slower.)
+void set_launch_shapes(gp_plan *p)
+{
+    const int64_t *grid = p->n;
+    const int64_t xl = gpssc::x_lines_per_wave(p->ax[0].chunk, grid[1] * grid[2]);
+    p->x_blocks = (int)((grid[1] * grid[2] + xl - 1) / xl);
+    p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
+    p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
+    p->pairs_y = pair_axis(p->dtype, grid, 1);
+    p->pairs_z = pair_axis(p->dtype, grid, 2);
+    if (p->pairs_y) {
+        p->xt2_y = strided_pair_columns(grid[0], p->ax[1].lanes, p->ax[1].chunk);
+        p->y2_blocks = (int)(((grid[0] + 2 * p->xt2_y - 1) / (2 * p->xt2_y)) * grid[2]);
+    }
+    if (p->pairs_z) {
+        p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
+        p->z2_blocks = (int)(((grid[0] + 2 * p->xt2_z - 1) / (2 * p->xt2_z)) * grid[1]);
     }
 }
 
@@ -513,27 +570,10 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
 {
     if (!out) return fail(GP_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (!valid_grid(grid)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
-    if (ndim < 1 || ndim > 3) return fail(GP_ERR_INVALID, "ndim must be 1, 2 or 3");
-    for (int a = ndim; a < 3; ++a)
-        if (grid[a] != 1) return fail(GP_ERR_INVALID, "axes beyond ndim must have one node");
-    if (!dx || !finite_pos(dx[0]) || !finite_pos(dx[1]) || !finite_pos(dx[2]))
-        return fail(GP_ERR_INVALID, "dx must be finite and > 0");
-    if (!finite_pos(dt)) return fail(GP_ERR_INVALID, "dt must be finite and > 0");
     const double om[3] = {gamma, nu, lambda};
-    for (double w : om)
-        if (!std::isfinite(w) || w < 0.0) return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
-    if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
-    if (mode != GP_MODE_IMAG && mode != GP_MODE_REAL) return fail(GP_ERR_INVALID, "unknown mode");
-    if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
-    if (real_storage(dtype) && mode != GP_MODE_IMAG)
-        return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
     int chunk[3], lanes[3];
-    for (int a = 0; a < 3; ++a)
-        if (!sweep_shape(grid[a], a, &chunk[a], &lanes[a], max_lanes_for(dtype, grid[a])))
-            return fail(GP_ERR_UNSUPPORTED, "grid line too long (Nx <= 1024, Ny, Nz <= 1024)");
-    if (grid[1] * grid[2] > 0x7fffffffLL || grid[1] > 65535 || grid[2] > 65535)
-        return fail(GP_ERR_UNSUPPORTED, "too many grid lines for one launch");
+    gp_status st = check_plan_args(ndim, grid, dx, dt, om, g, mode, dtype, chunk, lanes);
+    if (st != GP_OK) return st;
 
     gp_plan *p = new (std::nothrow) gp_plan();
     if (!p) return fail(GP_ERR_NOMEM, "host allocation failed");
@@ -593,27 +633,10 @@ gp_status gp_plan_create_nd(int ndim, const int64_t grid[3], const double dx[3],
         release(p);
         return fail_hip(e, "uploading the tables");
     }
-    fill_args<double>(p, p->xd, p->sd);
-    fill_args<float>(p, p->xf, p->sf);
-    // One block per line (x) or tile (y, z): blocks that finish early make
-    // room for the next ones, so the blocks on a compute unit drift out of
-    // step and their load, compute and store phases overlap.  (A grid of
-    // resident blocks looping over the work keeps them in lockstep and was
-    // measured slower.)
-    const int64_t xl = gpssc::x_lines_per_wave(p->ax[0].chunk, grid[1] * grid[2]);
-    p->x_blocks = (int)((grid[1] * grid[2] + xl - 1) / xl);
-    p->y_blocks = (int)(((grid[0] + p->xt_y - 1) / p->xt_y) * grid[2]);
-    p->z_blocks = (int)(((grid[0] + p->xt_z - 1) / p->xt_z) * grid[1]);
-    p->pairs_y = pair_axis(dtype, grid, 1);
-    p->pairs_z = pair_axis(dtype, grid, 2);
-    if (p->pairs_y) {
-        p->xt2_y = strided_pair_columns(grid[0], p->ax[1].lanes, p->ax[1].chunk);
-        p->y2_blocks = (int)(((grid[0] + 2 * p->xt2_y - 1) / (2 * p->xt2_y)) * grid[2]);
-    }
-    if (p->pairs_z) {
-        p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
-        p->z2_blocks = (int)(((grid[0] + 2 * p->xt2_z - 1) / (2 * p->xt2_z)) * grid[1]);
-    }
+    const cplx *zt[3] = {p->ax[0].zt.data(), p->ax[1].zt.data(), p->ax[2].zt.data()};
+    fill_args<double>(p, zt, p->xd, p->sd);
+    fill_args<float>(p, zt, p->xf, p->sf);
+    set_launch_shapes(p);
     *out = p;
     return GP_OK;
 }
@@ -706,7 +729,18 @@ gp_status gp_set_g(gp_plan *plan, double g)
 gp_status gp_set_stream(gp_plan *plan, void *hip_stream)
 {
     if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
-    plan->stream = static_cast<hipStream_t>(hip_stream);
+    hipStream_t next = static_cast<hipStream_t>(hip_stream);
+    if (next == plan->stream) return GP_OK;
+    // work queued later on the new stream starts after everything already
+    // queued on the old one: both use the plan's scratch (the pending
+    // 1/sqrt(N), the partial sums, the error flag)
+    DeviceGuard guard(plan->device);
+    hipError_t e = hipSuccess;
+    if (!plan->ev_switch) e = hipEventCreateWithFlags(&plan->ev_switch, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_switch, plan->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, plan->ev_switch, 0);
+    if (e != hipSuccess) return fail_hip(e, "ordering the new stream after the old one");
+    plan->stream = next;
     return GP_OK;
 }
 
@@ -921,3 +955,4 @@ gp_status gp_profile_read(gp_plan *p, double *ms, int64_t *launches)
 }
 
 }  // extern "C"
+

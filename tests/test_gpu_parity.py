@@ -230,6 +230,28 @@ def test_runs_on_a_side_stream():
     assert np.array_equal(to_host(out), ref)
 
 
+def test_stream_switches_between_calls_keep_the_order():
+    """gp_set_stream (called by Plan.step for the current torch stream) must
+    order the new stream after the work already queued on the old one: the
+    calls share the plan's pending 1/sqrt(N) and partial sums.  Steps queued
+    on three streams in turn, with no synchronisation between them, equal
+    the same steps on one stream bitwise."""
+    grid, dx, dt, omega, g = (160, 128, 96), (0.2, 0.2, 0.2), 0.004, (1.0, 1.3, 1.7), 200.0
+    psi0 = inputs.smooth_random_state(grid, dx, omega, seed=5)
+    ref, _ = gpu_run(psi0, grid, dx, dt, omega, g, "imag", "c128", 40, chunks=8)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    psi = to_dev(psi0, "c128")
+    torch.cuda.synchronize()
+    with gp.Plan(grid, dx, dt, *omega, g, mode="imag") as plan:
+        for c in range(8):
+            with torch.cuda.stream(streams[c % 3]):
+                plan.step(psi, 5)
+        with torch.cuda.stream(streams[7 % 3]):
+            plan.sync()
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(psi), ref)
+
+
 @pytest.mark.parametrize("mode", ["real", "imag"])
 @pytest.mark.parametrize("grid", [(24, 300, 18), (16, 12, 520), (34, 264, 260)], ids=lambda g: "x".join(map(str, g)))
 def test_complex64_column_pairs_equal_single_columns(grid, mode):
