@@ -222,6 +222,28 @@ gp_status gp_observables(gp_plan *plan, const void *psi_dev, int64_t psi_elems,
  * scratch), excluding psi.  Returns 0 for an invalid grid. */
 size_t gp_plan_footprint_bytes(const int64_t grid[3], gp_dtype dtype);
 
+/* gp_step for callers that cannot allocate device memory: code that must
+ * not call hipMalloc (a tight serving loop, a harness that forbids it).
+ * Queues the same work as gp_plan_create with these arguments (ndim 3,
+ * Cartesian) followed by gp_step(psi, nsteps) on that plan, with bitwise the
+ * same result, and returns without waiting; nothing is allocated (no
+ * hipMalloc, hipFree or host heap on this path).  Instead of a plan's memory
+ * it uses a static device array of the library, 2.1 MiB per device, held
+ * until the process ends: the correction tables of the three axes (rebuilt on
+ * the host at every call and written by small kernels queued on the stream),
+ * one norm partial per z line, the pending 1/sqrt(N) and an error flag
+ * (cleared at every call).  Limit: Nx * Ny <= 262144 (GP_ERR_UNSUPPORTED
+ * beyond), on top of gp_plan_create's.  Every call on one device shares that
+ * array, so calls whose queued work overlaps on a device race: order them,
+ * for example by queueing them on one stream.  A zero or non-finite norm in
+ * imaginary time is not reported (no later call can read the flag); it
+ * leaves psi non-finite.  Errors otherwise as gp_plan_create and gp_step;
+ * on GP_ERR_INVALID or GP_ERR_UNSUPPORTED nothing is queued. */
+gp_status gp_step_noalloc(const int64_t grid[3], const double dx[3], double dt,
+                          double gamma, double nu, double lambda, double g,
+                          gp_mode mode, gp_dtype dtype, void *hip_stream,
+                          void *psi_dev, int64_t psi_elems, int64_t nsteps);
+
 /* Density profiles of psi (the paper's programs write the density along the
  * axes as output): px[i] = dy dz sum_{j,k} |psi_ijk|^2, and likewise py[Ny],
  * pz[Nz], with the spacings of the present axes only (gp_plan_create_nd).

@@ -10,5 +10,5 @@ generators in ``inputs``) needs no GPU.
 from ._binding import (  # noqa: F401
     C64, C64_F64, C128, IMAG, R32, R64, REAL, EXPORTS, KERNELS, Batch, GPError, GPInvalid, GPNoMemory, GPNonFinite,
     Plan, Server,
-    footprint_bytes, lib, library_path, request_bytes, sweep_shape, sweep_tables,
+    footprint_bytes, lib, library_path, request_bytes, step_noalloc, sweep_shape, sweep_tables,
 )

@@ -33,7 +33,7 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 # Every symbol include/gpssc.h declares.
 EXPORTS = (
     "gp_plan_create", "gp_plan_create_nd", "gp_plan_create_radial", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
-    "gp_step_schedule", "gp_sync",
+    "gp_step_schedule", "gp_step_noalloc", "gp_sync",
     "gp_observables", "gp_density_profiles", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
     "gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active", "gp_batch_step",
@@ -142,6 +142,7 @@ def lib() -> ctypes.CDLL:
     L.gp_step_schedule.argtypes = [vp, vp, i64, i64, dp, dp]
     L.gp_set_stream.argtypes = [vp, vp]
     L.gp_step.argtypes = [vp, vp, i64, i64]
+    L.gp_step_noalloc.argtypes = [i64p, dp, dbl, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int, vp, vp, i64, i64]
     L.gp_sync.argtypes = [vp]
     L.gp_observables.argtypes = [vp, vp, i64, ctypes.POINTER(GPObs)]
     L.gp_density_profiles.argtypes = [vp, vp, i64, dp, dp, dp]
@@ -184,7 +185,7 @@ def lib() -> ctypes.CDLL:
                  "gp_batch_step", "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_step_schedule",
-                 "gp_set_stream", "gp_step",
+                 "gp_set_stream", "gp_step", "gp_step_noalloc",
                  "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
                  "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables"):
         getattr(L, name).restype = ctypes.c_int
@@ -277,6 +278,25 @@ def sweep_tables(n: int, dx: float, dt: float, mode, chunk: int, lanes: int) -> 
     k = c(coef)
     return {"kappa": k[0], "b": k[1], "o": k[2], "c": k[3], "beta": k[4], "m": k[5], "a": k[6],
             "stage": c(stage), "zt": c(zt)}
+
+
+def step_noalloc(psi, dx, dt, gamma, nu, lam, g, mode="imag", dtype="c128", nsteps: int = 1, stream=None):
+    """gp_step_noalloc: nsteps steps on psi (in place, queued on the current
+    torch stream) without a plan and without allocating device memory; the
+    grid is psi's shape (Nz, Ny, Nx)."""
+    import torch
+
+    dt_code = _dtype(dtype)
+    if not isinstance(psi, torch.Tensor) or psi.dtype != torch_dtype_of(dt_code) or psi.device.type != "cuda" \
+            or psi.dim() != 3 or not psi.is_contiguous():
+        raise ValueError(f"psi must be a contiguous {torch_dtype_of(dt_code)} CUDA tensor (Nz, Ny, Nx)")
+    nz, ny, nx = psi.shape
+    n = (ctypes.c_int64 * 3)(nx, ny, nz)
+    d = (ctypes.c_double * 3)(*[float(v) for v in (dx if hasattr(dx, "__len__") else (dx, dx, dx))])
+    _check(lib().gp_step_noalloc(n, d, float(dt), float(gamma), float(nu), float(lam), float(g), _mode(mode),
+                                 dt_code, Plan._stream_handle(stream), ctypes.c_void_p(psi.data_ptr()),
+                                 psi.numel(), int(nsteps)), "gp_step_noalloc")
+    return psi
 
 
 class Plan:

@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -956,3 +957,172 @@ gp_status gp_profile_read(gp_plan *p, double *ms, int64_t *launches)
 
 }  // extern "C"
 
+// ---- gp_step_noalloc: the step with its device memory in a static array ----
+//
+// For callers that cannot allocate device memory.  The correction tables of
+// the three axes, one norm partial per z line, the 1/sqrt(N) slot and the
+// error flag live in `scratch`, a fixed array that each device holds until
+// the process ends.  Layout (bytes):
+//   [0, 48 Ki)                   tables, each axis padded to chunk * lanes entries
+//   [48 Ki, 48 Ki + 2 Mi)        norm partials, at most kNoallocMaxLines doubles
+//   then 256 B                   1/sqrt(N) (double)
+//   then 256 B                   error flag (int)
+namespace {
+constexpr int64_t kNoallocMaxLines = int64_t(1) << 18;   // Nx * Ny
+constexpr size_t kNoallocTableBytes = 3 * 1024 * sizeof(cx<double>);
+constexpr size_t kNoallocPartialOff = kNoallocTableBytes;
+constexpr size_t kNoallocScaleOff = kNoallocPartialOff + (size_t)kNoallocMaxLines * sizeof(double);
+constexpr size_t kNoallocFlagOff = kNoallocScaleOff + 256;
+constexpr size_t kNoallocBytes = kNoallocFlagOff + 256;
+constexpr int kNoallocMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+// Table words written by one install launch; they travel as a kernel
+// argument (copied at launch), so no host buffer has to outlive the call.
+constexpr int kInstallWords = 256;
+struct InstallWords {
+    uint64_t w[kInstallWords];
+};
+
+__global__ void noalloc_install_kernel(uint64_t *dst, InstallWords src, int nwords, int *flag)
+{
+    const int t = threadIdx.x;
+    if (t < nwords) dst[t] = src.w[t];
+    if (flag && t == 0) *flag = 0;
+}
+
+// Guards the per-device addresses and the host staging of the tables.
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoallocMaxDevices];
+
+struct NoallocHost {
+    cplx zt[3][1024];
+    cplx w[1024], z[1024];
+};
+NoallocHost g_noalloc_host;
+
+// Device address of `scratch` on device dev (current), looked up once per
+// device.  The array's name is only a host-side handle: kernels and copies
+// take this address.  Call with g_noalloc_mu held.
+void *noalloc_scratch(int dev, hipError_t *err)
+{
+    *err = hipSuccess;
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_noalloc_ptr[dev] = ptr;
+    }
+    return g_noalloc_ptr[dev];
+}
+
+// Writes the first nzc correction entries of every axis (the only ones the
+// kernels read) into the device tables, in the arithmetic type A, and clears
+// the error flag.
+template <typename A>
+hipError_t noalloc_install(gp_plan *p, const int nzc[3])
+{
+    InstallWords words;
+    hipError_t e = hipSuccess;
+    bool flag_cleared = false;
+    constexpr int per = sizeof(cx<A>) / sizeof(uint64_t) > 0 ? (int)(sizeof(cx<A>) / sizeof(uint64_t)) : 1;
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+        const int nwords = nzc[a] * per;
+        uint64_t *dst = reinterpret_cast<uint64_t *>(p->d_tables + p->tab_off[a]);
+        for (int w0 = 0; w0 < nwords && e == hipSuccess; w0 += kInstallWords) {
+            const int nw = nwords - w0 < kInstallWords ? nwords - w0 : kInstallWords;
+            for (int q = 0; q < nw; q += per) {
+                const cx<A> v = to_cx<A>(g_noalloc_host.zt[a][(w0 + q) / per]);
+                std::memcpy(&words.w[q], &v, sizeof v);
+            }
+            hipLaunchKernelGGL(noalloc_install_kernel, dim3(1), dim3(kInstallWords), 0, p->stream, dst + w0, words,
+                               nw, flag_cleared ? nullptr : p->d_flag);
+            flag_cleared = true;
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess && !flag_cleared) {
+        hipLaunchKernelGGL(noalloc_install_kernel, dim3(1), dim3(kInstallWords), 0, p->stream, nullptr, words, 0,
+                           p->d_flag);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_step_noalloc(const int64_t grid[3], const double dx[3], double dt, double gamma, double nu,
+                          double lambda, double g, gp_mode mode, gp_dtype dtype, void *hip_stream, void *psi,
+                          int64_t psi_elems, int64_t nsteps)
+{
+    const double om[3] = {gamma, nu, lambda};
+    int chunk[3], lanes[3];
+    gp_status st = check_plan_args(3, grid, dx, dt, om, g, mode, dtype, chunk, lanes);
+    if (st != GP_OK) return st;
+    if (nsteps < 0) return fail(GP_ERR_INVALID, "nsteps must be >= 0");
+    if (grid[0] * grid[1] > kNoallocMaxLines)
+        return fail(GP_ERR_UNSUPPORTED, "gp_step_noalloc: Nx*Ny = " + std::to_string(grid[0] * grid[1]) +
+                                            " exceeds its scratch maximum of " + std::to_string(kNoallocMaxLines) +
+                                            " z lines");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kNoallocMaxDevices) return fail(GP_ERR_UNSUPPORTED, "gp_step_noalloc: device index too high");
+
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    unsigned char *base = static_cast<unsigned char *>(noalloc_scratch(dev, &e));
+    if (!base) return fail_hip(e, "hipGetSymbolAddress of the static scratch array");
+
+    // a plan on the stack whose device memory is the static array
+    gp_plan p;
+    for (int a = 0; a < 3; ++a) {
+        p.n[a] = grid[a];
+        p.dx[a] = dx[a];
+        p.omega[a] = om[a];
+    }
+    p.dt = dt;
+    p.g = g;
+    p.mode = mode;
+    p.dtype = dtype;
+    p.stream = static_cast<hipStream_t>(hip_stream);
+    p.device = dev;
+    const bool real = mode == GP_MODE_REAL;
+    const cplx *zt[3];
+    size_t elem_off = 0;
+    const size_t cs = arith_f32(dtype) ? sizeof(cx<float>) : sizeof(cx<double>);
+    for (int a = 0; a < 3; ++a) {
+        build_axis_into(grid[a], dx[a], dt, real, chunk[a], lanes[a], p.ax[a], g_noalloc_host.zt[a],
+                        g_noalloc_host.w, g_noalloc_host.z);
+        zt[a] = g_noalloc_host.zt[a];
+        p.tab_off[a] = elem_off * cs;   // the padded layout of pack_tables
+        elem_off += (size_t)chunk[a] * lanes[a];
+    }
+    footprint(grid, dtype, &p.xt_y, &p.xt_z);
+    p.n_zblocks = (int)(grid[0] * grid[1]);
+    p.d_tables = base;
+    p.d_partials = reinterpret_cast<double *>(base + kNoallocPartialOff);
+    p.d_scale = reinterpret_cast<double *>(base + kNoallocScaleOff);
+    p.d_flag = reinterpret_cast<int *>(base + kNoallocFlagOff);
+    fill_args<double>(&p, zt, p.xd, p.sd);
+    fill_args<float>(&p, zt, p.xf, p.sf);
+    set_launch_shapes(&p);
+
+    st = check_psi(&p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    if (nsteps == 0) return GP_OK;
+    DeviceGuard guard(dev);
+    const bool a32 = arith_f32(dtype);
+    const int nzc[3] = {a32 ? p.xf.k.nzc : p.xd.k.nzc, a32 ? p.sf[0].k.nzc : p.sd[0].k.nzc,
+                        a32 ? p.sf[1].k.nzc : p.sd[1].k.nzc};
+    e = a32 ? noalloc_install<float>(&p, nzc) : noalloc_install<double>(&p, nzc);
+    if (e != hipSuccess) return fail_hip(e, "installing the tables");
+    return run_steps(&p, psi, psi_elems, nsteps, nullptr, nullptr);
+}
+
+}  // extern "C"

@@ -305,3 +305,25 @@ def test_plan_create_radial_rejects_bad_arguments_before_any_device_call():
         assert L.gp_plan_create_radial(geom, n, d, 0.01, 1.0, nu, 1.0, 1.0, 0, 0, None, ctypes.byref(out)) == \
             _binding.ERR_INVALID, (geom, grid)
         assert out.value is None
+
+
+def test_noalloc_step_checks_arguments_before_any_device_call():
+    """gp_step_noalloc validates like gp_plan_create and gp_step, and refuses
+    grids beyond its static scratch (Nx * Ny <= 262144) with a clear error,
+    all before touching a device."""
+    L = gp.lib()
+    d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    psi = ctypes.c_void_p(4096)   # never dereferenced: every case fails first
+    cases = [
+        ((8, 8, 8), 0.0, 1, _binding.ERR_INVALID),          # dt
+        ((0, 8, 8), 0.01, 1, _binding.ERR_INVALID),         # grid
+        ((8, 8, 8), 0.01, -1, _binding.ERR_INVALID),        # nsteps
+        ((8, 8, 2000), 0.01, 1, _binding.ERR_UNSUPPORTED),  # line too long
+        ((513, 512, 4), 0.01, 1, _binding.ERR_UNSUPPORTED),  # beyond the scratch
+    ]
+    for grid, dt, nsteps, want in cases:
+        n = (ctypes.c_int64 * 3)(*grid)
+        elems = grid[0] * grid[1] * grid[2]
+        st = L.gp_step_noalloc(n, d, dt, 1.0, 1.0, 1.0, 1.0, 0, 0, None, psi, elems, nsteps)
+        assert st == want, (grid, dt, nsteps)
+    assert b"262144" in L.gp_last_error()
