@@ -160,6 +160,29 @@ gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const doubl
                                 gp_mode mode, gp_dtype dtype, void *hip_stream,
                                 gp_plan **out);
 
+/* How the y and z sweeps solve their lines.
+ * GP_SWEEP_CHUNKED : a block of threads holds neighbouring lines, each cut
+ *                    into contiguous chunks; the chunks' carries come from a
+ *                    parallel (Kogge-Stone) scan.  Exact for every system.
+ * GP_SWEEP_STREAM  : one thread per line (or pair of complex64 lines) walks
+ *                    the line in blocks of B = 8, 12 or 16 points; the
+ *                    backward recurrence of a block starts B - 1 points past
+ *                    its end, which is exact to rounding when |c|^B is below
+ *                    2^-60 (FP64 arithmetic) or 2^-30 (FP32), c the decay
+ *                    ratio of the Crank-Nicolson inverse of the axis (small
+ *                    for small dt / dx^2).  An axis where no B qualifies
+ *                    keeps the chunked scan.
+ * GP_SWEEP_AUTO    : the library's choice per axis (the default); at present
+ *                    the chunked scan, which measured at least as fast on
+ *                    every grid tried.
+ * Both solve the same matrices; results agree to rounding, not bitwise. */
+typedef enum { GP_SWEEP_AUTO = 0, GP_SWEEP_CHUNKED = 1, GP_SWEEP_STREAM = 2 } gp_sweep;
+
+/* Sets the y/z strategy of a plan's later steps (calcluy, calcluz).  The
+ * symmetric-trap plans keep the chunked scan.  gp_plan_describe shows the
+ * choice per axis. */
+gp_status gp_plan_set_sweep(gp_plan *plan, gp_sweep strategy);
+
 /* Frees the plan's tables and scratch after waiting for its stream.
  * NULL-safe. */
 gp_status gp_plan_destroy(gp_plan *plan);
@@ -290,7 +313,9 @@ typedef struct gp_batch gp_batch;
 
 enum {
     GP_BATCH_GRAPH = 1,  /* capture one step of all classes in a HIP graph and replay it */
-    GP_BATCH_TUNE = 2    /* time the y/z block widths per class at creation (scratch memory) */
+    GP_BATCH_TUNE = 2,   /* time the y/z block widths per class at creation (scratch memory) */
+    GP_BATCH_FINISH_F64 = 4  /* imaginary-time GP_C64 / GP_R32 batches: gp_batch_solve_imag finishes
+                                each solve in FP64 storage (see there) */
 };
 
 /* Creates a batch of nsolves solves.  Per solve i: grids[3i..3i+2] (Nx, Ny,
@@ -328,7 +353,16 @@ gp_status gp_batch_observables(gp_batch *batch, gp_obs *out);
  * whose mu moved by less than tol since the previous evaluation stops (is
  * no longer advanced).  Ends when all solves stopped or after max_steps.
  * Fills out[i] (last evaluation), steps[i] (steps taken) and converged[i].
- * Every solve is active again on return. */
+ * Every solve is active again on return.
+ * With GP_BATCH_FINISH_F64 the float storage carries a solve only until its
+ * mu moves by less than 100 tol between evaluations; its state is then
+ * copied exactly to double storage of the batch's own (complex128 for
+ * GP_C64, double for GP_R32) and the solve continues there, on FP64
+ * arithmetic, until the rule above holds for two FP64 evaluations.  A float
+ * state near convergence stops following the FP64 iteration (each step's
+ * change falls below half a float ulp), so this is what brings mu to FP64
+ * accuracy.  The final state is rounded back into the caller's float
+ * buffer; out[i] is the evaluation of the FP64 state. */
 gp_status gp_batch_solve_imag(gp_batch *batch, double tol, int64_t check_every, int64_t max_steps,
                               gp_obs *out, int64_t *steps, unsigned char *converged);
 
@@ -356,7 +390,11 @@ gp_status gp_batch_describe(const gp_batch *batch, char *buf, size_t len);
 typedef struct gp_server gp_server;
 
 enum {
-    GP_SERVER_GRAPH = 1  /* capture one step of the resident set in a HIP graph, re-captured when it changes */
+    GP_SERVER_GRAPH = 1,     /* capture one step of the resident set in a HIP graph, re-captured when it changes */
+    GP_SERVER_REAL_AUTO = 2  /* on a GP_C64 or GP_C128 server, an imaginary-time request whose initial state has
+                                no imaginary part (every imaginary part exactly 0, checked in gp_server_submit)
+                                runs on real storage, as with real_state, while its host buffers stay complex:
+                                the result is the one real_state gives, written with zero imaginary parts */
 };
 
 typedef struct {

@@ -33,7 +33,7 @@ KERNELS = ("nu_x", "y", "z", "norm", "scale", "obs")
 # Every symbol include/gpssc.h declares.
 EXPORTS = (
     "gp_plan_create", "gp_plan_create_nd", "gp_plan_create_radial", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_set_stream", "gp_step",
-    "gp_step_schedule", "gp_step_noalloc", "gp_sync",
+    "gp_step_schedule", "gp_step_noalloc", "gp_sync", "gp_plan_set_sweep",
     "gp_observables", "gp_density_profiles", "gp_plan_footprint_bytes", "gp_plan_describe", "gp_status_string",
     "gp_last_error", "gp_profile_enable", "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables",
     "gp_batch_create", "gp_batch_destroy", "gp_batch_set_psi", "gp_batch_set_active", "gp_batch_step",
@@ -44,7 +44,9 @@ EXPORTS = (
 
 BATCH_GRAPH = 1
 BATCH_TUNE = 2
+BATCH_FINISH_F64 = 4
 SERVER_GRAPH = 1
+SERVER_REAL_AUTO = 2
 
 
 class GPError(RuntimeError):
@@ -142,6 +144,7 @@ def lib() -> ctypes.CDLL:
     L.gp_step_schedule.argtypes = [vp, vp, i64, i64, dp, dp]
     L.gp_set_stream.argtypes = [vp, vp]
     L.gp_step.argtypes = [vp, vp, i64, i64]
+    L.gp_plan_set_sweep.argtypes = [vp, ctypes.c_int]
     L.gp_step_noalloc.argtypes = [i64p, dp, dbl, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int, vp, vp, i64, i64]
     L.gp_sync.argtypes = [vp]
     L.gp_observables.argtypes = [vp, vp, i64, ctypes.POINTER(GPObs)]
@@ -185,7 +188,7 @@ def lib() -> ctypes.CDLL:
                  "gp_batch_step", "gp_batch_observables", "gp_batch_solve_imag", "gp_batch_describe"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("gp_plan_create", "gp_plan_destroy", "gp_set_g", "gp_set_trap", "gp_step_schedule",
-                 "gp_set_stream", "gp_step", "gp_step_noalloc",
+                 "gp_set_stream", "gp_step", "gp_step_noalloc", "gp_plan_set_sweep",
                  "gp_sync", "gp_observables", "gp_plan_describe", "gp_profile_enable",
                  "gp_profile_read", "gp_sweep_shape", "gp_sweep_tables"):
         getattr(L, name).restype = ctypes.c_int
@@ -430,6 +433,12 @@ class Plan:
             self.omega = tuple(float(v) for v in t_arr[-1])
         return psi
 
+    SWEEPS = {"auto": 0, "chunked": 1, "stream": 2}
+
+    def set_sweep(self, strategy: str) -> None:
+        """y/z strategy of later steps: "auto", "chunked" or "stream"."""
+        _check(lib().gp_plan_set_sweep(self._handle, self.SWEEPS[strategy]), "gp_plan_set_sweep")
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(512)
         _check(lib().gp_plan_describe(self._handle, buf, len(buf)), "gp_plan_describe")
@@ -470,7 +479,7 @@ class Batch:
     3-tuple), dt, trap (gamma, nu, lambda), g.  All share mode and dtype.
     """
 
-    def __init__(self, specs, mode="imag", dtype="c128", graph=True, tune=False, stream=None):
+    def __init__(self, specs, mode="imag", dtype="c128", graph=True, tune=False, stream=None, finish_f64=False):
         import numpy as np
         import torch
 
@@ -489,7 +498,7 @@ class Batch:
         self.mode = _mode(mode)
         self.dtype = _dtype(dtype)
         self.torch_dtype = torch_dtype_of(self.dtype)
-        flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0)
+        flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0) | (BATCH_FINISH_F64 if finish_f64 else 0)
         self._handle = ctypes.c_void_p()
         self._psis = None
         dp = ctypes.POINTER(ctypes.c_double)
@@ -582,7 +591,7 @@ class Server:
     """
 
     def __init__(self, dtype="c64", hbm_budget: int = 8 << 30, max_slots: int = 64, check_every: int = 10,
-                 graph: bool = True):
+                 graph: bool = True, real_auto: bool = False):
         import atexit
         import weakref
 
@@ -596,7 +605,8 @@ class Server:
         self._handle = ctypes.c_void_p()
         self._held = {}
         _check(L.gp_server_create(self.dtype, int(hbm_budget), int(max_slots), self.check_every,
-                                  SERVER_GRAPH if graph else 0, ctypes.byref(self._handle)), "gp_server_create")
+                                  (SERVER_GRAPH if graph else 0) | (SERVER_REAL_AUTO if real_auto else 0),
+                                  ctypes.byref(self._handle)), "gp_server_create")
         if _servers is None:
             _servers = weakref.WeakSet()
             atexit.register(_close_servers)

@@ -79,6 +79,12 @@ struct gp_batch {
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
     int64_t steps_done = 0;
+
+    // GP_BATCH_FINISH_F64: the same solves in FP64 storage (complex128 for
+    // complex64, float64 for float32), on buffers of the batch's own
+    gp_batch *fin = nullptr;
+    unsigned char *d_shadow = nullptr;
+    std::vector<void *> shadow;
 };
 
 namespace {
@@ -93,6 +99,11 @@ bool bound(const gp_batch *b)
 void release(gp_batch *b)
 {
     if (!b) return;
+    if (b->fin) {
+        (void)hipStreamSynchronize(b->fin->own);
+        release(b->fin);
+    }
+    if (b->d_shadow) (void)hipFree(b->d_shadow);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (Class &c : b->cls)
@@ -302,6 +313,9 @@ hipError_t sync_out(gp_batch *b)
     return e;
 }
 
+gp_status solve_imag_finished(gp_batch *b, double tol, int64_t check_every, int64_t max_steps, gp_obs *out,
+                              int64_t *steps, unsigned char *converged);
+
 }  // namespace
 
 extern "C" {
@@ -318,7 +332,9 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
     if (real_storage(dtype) && mode != GP_MODE_IMAG)
         return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
-    if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE)) return fail(GP_ERR_INVALID, "unknown flags");
+    if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE | GP_BATCH_FINISH_F64)) return fail(GP_ERR_INVALID, "unknown flags");
+    if ((flags & GP_BATCH_FINISH_F64) && (mode != GP_MODE_IMAG || (dtype != GP_C64 && dtype != GP_R32)))
+        return fail(GP_ERR_INVALID, "GP_BATCH_FINISH_F64 is for imaginary-time batches in GP_C64 or GP_R32");
     for (int i = 0; i < nsolves; ++i) {
         if (!valid_grid(grids + 3 * i)) return fail(GP_ERR_INVALID, "grid sizes must be >= 1");
         if (!valid_params(dx + 3 * i, dt[i], traps + 3 * i, g[i]))
@@ -462,6 +478,41 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     if (e != hipSuccess) {
         release(b);
         return fail_hip(e, "setting up the batch");
+    }
+    if (flags & GP_BATCH_FINISH_F64) {
+        const gp_dtype fd = dtype == GP_C64 ? GP_C128 : GP_R64;
+        gp_status st = gp_batch_create(nsolves, grids, dx, dt, traps, g, mode, fd, flags & ~GP_BATCH_FINISH_F64,
+                                       hip_stream, &b->fin);
+        if (st != GP_OK) {
+            release(b);
+            return st;
+        }
+        std::vector<size_t> off((size_t)nsolves);
+        std::vector<int64_t> elems((size_t)nsolves);
+        size_t total = 0;
+        for (int i = 0; i < nsolves; ++i) {
+            off[(size_t)i] = total;
+            elems[(size_t)i] = b->s[(size_t)i].elems;
+            total += ((size_t)elems[(size_t)i] * storage_bytes(fd) + 255) / 256 * 256;
+        }
+        e = hipMalloc((void **)&b->d_shadow, total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            release(b);
+            return e == hipErrorOutOfMemory ? fail(GP_ERR_NOMEM, "hipMalloc of the FP64 states failed")
+                                            : fail_hip(e, "hipMalloc");
+        }
+        b->shadow.resize((size_t)nsolves);
+        for (int i = 0; i < nsolves; ++i) b->shadow[(size_t)i] = b->d_shadow + off[(size_t)i];
+        st = gp_batch_set_psi(b->fin, b->shadow.data(), elems.data());
+        if (st == GP_OK) {
+            std::vector<unsigned char> none((size_t)nsolves, 0);
+            st = gp_batch_set_active(b->fin, none.data());
+        }
+        if (st != GP_OK) {
+            release(b);
+            return st;
+        }
     }
     *out = b;
     return GP_OK;
@@ -607,6 +658,7 @@ gp_status gp_batch_solve_imag(gp_batch *b, double tol, int64_t check_every, int6
     if (b->mode != GP_MODE_IMAG) return fail(GP_ERR_INVALID, "gp_batch_solve_imag needs an imaginary-time batch");
     if (!(tol > 0.0) || check_every < 1 || max_steps < 1)
         return fail(GP_ERR_INVALID, "need tol > 0, check_every >= 1, max_steps >= 1");
+    if (b->fin) return solve_imag_finished(b, tol, check_every, max_steps, out, steps, converged);
     std::vector<unsigned char> act((size_t)b->n, 1);
     std::vector<double> last((size_t)b->n, NAN);
     for (int i = 0; i < b->n; ++i) {
@@ -666,3 +718,105 @@ gp_status gp_batch_describe(const gp_batch *b, char *buf, size_t len)
 }
 
 }  // extern "C"
+
+namespace {
+
+// gp_batch_solve_imag with GP_BATCH_FINISH_F64.  A solve runs in the batch's
+// float storage until its chemical potential moves by less than
+// kSwitchFactor * tol between two evaluations; its state is then copied
+// (exactly) to double storage and it continues in the FP64 batch, where the
+// stopping rule |delta mu| < tol applies to FP64 evaluations only.  At the
+// end each state is rounded back into the caller's float buffer; out[i]
+// holds the last evaluation (of the FP64 state for the solves that reached
+// it).
+constexpr double kSwitchFactor = 100.0;
+
+gp_status solve_imag_finished(gp_batch *b, double tol, int64_t check_every, int64_t max_steps, gp_obs *out,
+                              int64_t *steps, unsigned char *converged)
+{
+    const int n = b->n;
+    gp_batch *f = b->fin;
+    const gpssc::Prec p32 = static_cast<gpssc::Prec>(b->dtype), p64 = static_cast<gpssc::Prec>(f->dtype);
+    std::vector<unsigned char> act32((size_t)n, 1), act64((size_t)n, 0);
+    std::vector<int> phase((size_t)n, 0);   // 0 float, 1 double, 2 done
+    std::vector<double> last((size_t)n, NAN);
+    std::vector<gp_obs> o64((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        steps[i] = 0;
+        converged[i] = 0;
+    }
+    gp_status st = gp_batch_set_active(b, act32.data());
+    if (st == GP_OK) st = gp_batch_set_active(f, act64.data());
+    if (st == GP_OK) st = gp_batch_observables(b, out);
+    if (st != GP_OK) return st;
+    for (int i = 0; i < n; ++i) last[(size_t)i] = out[i].mu;
+    DeviceGuard guard(b->device);
+    auto to_f64 = [&](int i) {
+        return gpssc::launch_convert(p64, p32, b->shadow[(size_t)i], b->s[(size_t)i].psi, b->s[(size_t)i].elems,
+                                     b->caller);
+    };
+    auto to_f32 = [&](int i) {
+        return gpssc::launch_convert(p32, p64, b->s[(size_t)i].psi, b->shadow[(size_t)i], b->s[(size_t)i].elems,
+                                     b->caller);
+    };
+    int64_t done = 0;
+    int left = n;
+    while (left > 0 && done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        int n32 = 0, n64 = 0;
+        for (int i = 0; i < n; ++i) {
+            n32 += act32[(size_t)i];
+            n64 += act64[(size_t)i];
+        }
+        if (n32) st = gp_batch_step(b, k);
+        if (st == GP_OK && n64) st = gp_batch_step(f, k);
+        if (st == GP_OK && n32) st = gp_batch_observables(b, out);
+        if (st == GP_OK && n64) st = gp_batch_observables(f, o64.data());
+        if (st != GP_OK) return st;
+        done += k;
+        bool changed = false;
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            if (phase[(size_t)i] == 2) continue;
+            steps[i] = done;
+            if (phase[(size_t)i] == 1) out[i] = o64[(size_t)i];
+            const double mu = out[i].mu;
+            if (phase[(size_t)i] == 0 && std::fabs(mu - last[(size_t)i]) < kSwitchFactor * tol) {
+                e = to_f64(i);
+                phase[(size_t)i] = 1;
+                act32[(size_t)i] = 0;
+                act64[(size_t)i] = 1;
+                changed = true;
+                last[(size_t)i] = NAN;   // two FP64 evaluations before the rule applies
+                continue;
+            }
+            if (phase[(size_t)i] == 1 && std::fabs(mu - last[(size_t)i]) < tol) {
+                converged[i] = 1;
+                phase[(size_t)i] = 2;
+                act64[(size_t)i] = 0;
+                --left;
+                changed = true;
+                e = to_f32(i);
+            }
+            last[(size_t)i] = mu;
+        }
+        if (e != hipSuccess) return fail_hip(e, "moving a state between float and double storage");
+        if (changed && left > 0) {
+            st = gp_batch_set_active(b, act32.data());
+            if (st == GP_OK) st = gp_batch_set_active(f, act64.data());
+            if (st != GP_OK) return st;
+        }
+    }
+    // the solves stopped by the step cap in FP64 storage go back too
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        if (phase[(size_t)i] == 1) e = to_f32(i);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->caller);
+    if (e != hipSuccess) return fail_hip(e, "moving the states back to float storage");
+    std::vector<unsigned char> none((size_t)n, 0);
+    st = gp_batch_set_active(f, none.data());
+    if (st != GP_OK) return st;
+    return gp_batch_set_active(b, nullptr);
+}
+
+}  // namespace

@@ -375,6 +375,13 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int
                           void *psi, const void *args, const void *zt, double *partials, bool xcd_ranges,
                           hipStream_t stream);
 
+// calcluy / calcluz streamed along the lines (sweep_stream.hip): one lane per
+// column (cols = 1) or column pair (cols = 2: complex64 with FP32 arithmetic,
+// nx and both strides even, psi 16-byte aligned), blocks of blk points (8,
+// 12 or 16), nouter * nx columns.  partials as in launch_strided.
+hipError_t launch_stream(Prec prec, bool real, int blk, int cols, int nouter, void *psi, const void *args,
+                         const void *zt, double *partials, hipStream_t stream);
+
 // calcnorm: sums `n` partials (each times weights[b] when weights is not
 // NULL) in a fixed order, writes 1/sqrt(dv*sum) to *scale and raises *flag
 // if the norm is not finite and positive.
@@ -400,6 +407,12 @@ hipError_t launch_radial_observables(Prec prec, const void *psi, const RadialObs
 // psi <- psi * (*scale)
 hipError_t launch_scale(Prec prec, void *psi, int64_t elems, const double *scale,
                         hipStream_t stream);
+
+// psi between storage types: float <-> double of one kind ((C128, C64),
+// (R64, R32); exact upwards, rounded to nearest downwards) or complex <->
+// real of one precision ((C64, R32), (C128, R64); the real part, or a zero
+// imaginary part).
+hipError_t launch_convert(Prec to, Prec from, void *dst, const void *src, int64_t elems, hipStream_t stream);
 
 // calcmuen + calcrms raw sums: partials [nblocks][OBS_NSUMS] then a fixed
 // order final sum into sums[OBS_NSUMS].

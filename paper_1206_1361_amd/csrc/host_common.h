@@ -200,6 +200,34 @@ inline void build_axis(int64_t n, double dx, double dt, bool real, int chunk, in
     build_axis_into(n, dx, dt, real, chunk, lanes, t, t.zt.data(), w.data(), z.data());
 }
 
+// Streaming y/z sweep (sweep_stream.hip): the backward recurrence of a
+// block of B points starts B - 1 points past the block's end from zero, which
+// leaves an error of |a|^B times the line's values at the block's last point.
+// Block length of an axis: the smallest B in {8, 12, 16} with |a|^B at most
+// 2^-60 (FP64 arithmetic) or 2^-30 (FP32), far below the rounding of the
+// result; 0 when even 16 is not enough (only the chunked scan is exact then).
+inline int stream_block_len(const AxisTables &t, bool f32)
+{
+    const double lim = std::ldexp(1.0, f32 ? -30 : -60);
+    const double r = std::abs(t.a);
+    for (int b : {8, 12, 16})
+        if (std::pow(r, (double)b) <= lim) return b;
+    return 0;
+}
+
+// Whether a y/z axis is streamed by default: never, so far.  On the
+// 512x512x384 grid the streamed sweeps measured no faster than the chunked
+// scan (complex128 y 0.583 vs 0.583 ms, z 0.704 vs 0.608 ms; complex64 y
+// 0.309 vs 0.302, z 0.324 vs 0.301), and a build of both with the arithmetic
+// removed showed the same order, so their access patterns, not the
+// arithmetic, set the limit.
+inline bool stream_by_default(int blk, gp_dtype dtype)
+{
+    (void)blk;
+    (void)dtype;
+    return false;
+}
+
 template <typename A>
 inline cx<A> to_cx(cplx v) { return cx<A>{(A)v.real(), (A)v.imag()}; }
 

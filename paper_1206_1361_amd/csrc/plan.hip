@@ -54,6 +54,9 @@ struct gp_plan {
     // pairs (16-byte rows per thread) whenever psi is 16-byte aligned
     bool pairs_y = false, pairs_z = false;
     int xt2_y = 0, xt2_z = 0, y2_blocks = 0, z2_blocks = 0;
+    // y/z strategy: block length of the streaming sweep, or 0 for the
+    // chunked scan; stream_ok: the longest admissible block (0: none)
+    int blk_y = 0, blk_z = 0, blk_ok_y = 0, blk_ok_z = 0;
 
     unsigned char *d_tables = nullptr;
     size_t tab_off[3];
@@ -267,6 +270,22 @@ gp_status check_plan_args(int ndim, const int64_t grid[3], const double dx[3], d
     return GP_OK;
 }
 
+// y/z strategy of a plan (the radial plans keep the chunked scan on their
+// Cartesian z axis).
+void set_sweep(gp_plan *p, gp_sweep s)
+{
+    const int ok[2] = {p->blk_ok_y, p->blk_ok_z};
+    int *blk[2] = {&p->blk_y, &p->blk_z};
+    for (int a = 0; a < 2; ++a) {
+        if (s == GP_SWEEP_CHUNKED)
+            *blk[a] = 0;
+        else if (s == GP_SWEEP_STREAM)
+            *blk[a] = ok[a];
+        else
+            *blk[a] = stream_by_default(ok[a], p->dtype) ? ok[a] : 0;
+    }
+}
+
 // Blocks per sweep and the complex64 column pairs, from the grid, the dtype
 // and the chunking (p->ax, p->xt_y, p->xt_z set).  One block per line (x)
 // or tile (y, z): blocks that finish early make room for the next ones, so
@@ -290,6 +309,10 @@ void set_launch_shapes(gp_plan *p)
         p->xt2_z = strided_pair_columns(grid[0], p->ax[2].lanes, p->ax[2].chunk);
         p->z2_blocks = (int)(((grid[0] + 2 * p->xt2_z - 1) / (2 * p->xt2_z)) * grid[1]);
     }
+    const bool f32 = arith_f32(p->dtype);
+    p->blk_ok_y = p->ndim >= 2 ? stream_block_len(p->ax[1], f32) : 0;
+    p->blk_ok_z = p->ndim >= 3 ? stream_block_len(p->ax[2], f32) : 0;
+    set_sweep(p, GP_SWEEP_AUTO);
 }
 
 gp_status check_psi(const gp_plan *p, const void *psi, int64_t elems)
@@ -381,6 +404,9 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
     const int nd = p->ndim;
     const bool aligned16 = reinterpret_cast<uintptr_t>(psi) % 16 == 0;
     const bool pair_y = p->pairs_y && aligned16, pair_z = p->pairs_z && aligned16;
+    // the streamed sweeps of complex64 (FP32 arithmetic) take column pairs
+    // whenever nx is even and psi 16-byte aligned
+    const bool spair = p->dtype == GP_C64 && p->n[0] % 2 == 0 && aligned16;
     double dv = 1.0;
     for (int a = 0; a < nd; ++a) dv *= p->dx[a];
     // the last sweep leaves the norm partials, one per line along its axis
@@ -410,6 +436,9 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         if (e != hipSuccess) break;
         if (nd >= 2) {
             e = timed(p, GP_KERNEL_Y, [&] {
+                if (p->blk_y)
+                    return gpssc::launch_stream(prec, real, p->blk_y, spair ? 2 : 1, (int)p->n[2], psi, yargs,
+                                                T + p->tab_off[1], nd == 2 ? parts : nullptr, p->stream);
                 return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair_y ? p->xt2_y : p->xt_y,
                                              pair_y ? 2 : 1, (int)p->n[2], pair_y ? p->y2_blocks : p->y_blocks,
                                              psi, yargs, T + p->tab_off[1], nd == 2 ? parts : nullptr,
@@ -419,6 +448,9 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         }
         if (nd == 3) {
             e = timed(p, GP_KERNEL_Z, [&] {
+                if (p->blk_z)
+                    return gpssc::launch_stream(prec, real, p->blk_z, spair ? 2 : 1, (int)p->n[1], psi, zargs,
+                                                T + p->tab_off[2], parts, p->stream);
                 return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
                                              pair_z ? 2 : 1, (int)p->n[1], pair_z ? p->z2_blocks : p->z_blocks,
                                              psi, zargs, T + p->tab_off[2], parts, false, p->stream);
@@ -660,6 +692,8 @@ gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const doubl
     gp_plan *p = *out;
     *out = nullptr;
     p->geom = geom;
+    p->blk_ok_y = p->blk_ok_z = 0;   // the radial plans keep the chunked scan
+    set_sweep(p, GP_SWEEP_AUTO);
     const int chunk = p->ax[0].chunk;
     const int npad = gpssc::kWave * chunk;
     std::vector<cplx> tab;
@@ -908,7 +942,11 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     char cols[2][64];
     for (int a = 0; a < 2; ++a) {
         const int xt = a ? p->xt_z : p->xt_y, blocks = a ? p->z_blocks : p->y_blocks;
-        if (a ? p->pairs_z : p->pairs_y)
+        const int blk = a ? p->blk_z : p->blk_y;
+        if (blk)
+            std::snprintf(cols[a], sizeof cols[a], "streamed in blocks of %d%s", blk,
+                          p->dtype == GP_C64 && p->n[0] % 2 == 0 ? ", column pairs when 16-byte aligned" : "");
+        else if (a ? p->pairs_z : p->pairs_y)
             std::snprintf(cols[a], sizeof cols[a], "%d cols in pairs, %d blocks", 2 * (a ? p->xt2_z : p->xt2_y),
                           a ? p->z2_blocks : p->y2_blocks);
         else
@@ -922,6 +960,15 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
                   p->mode == GP_MODE_REAL ? "real" : "imag", dt, p->ax[0].chunk, nst[0], nzc[0],
                   p->x_blocks, p->ax[1].chunk, p->ax[1].lanes, nst[1], nzc[1], cols[0],
                   p->ax[2].chunk, p->ax[2].lanes, nst[2], nzc[2], cols[1]);
+    return GP_OK;
+}
+
+gp_status gp_plan_set_sweep(gp_plan *p, gp_sweep strategy)
+{
+    if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
+    if (strategy != GP_SWEEP_AUTO && strategy != GP_SWEEP_CHUNKED && strategy != GP_SWEEP_STREAM)
+        return fail(GP_ERR_INVALID, "unknown sweep strategy");
+    set_sweep(p, strategy);
     return GP_OK;
 }
 

@@ -354,6 +354,57 @@ hipError_t launch_scale(Prec prec, void *psi, int64_t elems, const double *scale
     });
 }
 
+// psi copied between storage types: float <-> double of one kind (exact
+// upwards, rounded to nearest downwards), or complex <-> real of one
+// precision (the real part; a zero imaginary part).
+template <typename D, typename S>
+__global__ void __launch_bounds__(kReduceThreads)
+convert_kernel(D *__restrict__ dst, const S *__restrict__ src, int64_t elems)
+{
+    using R = typename storage_traits<D>::real;
+    for (int64_t p = (int64_t)blockIdx.x * kReduceThreads + threadIdx.x; p < elems;
+         p += (int64_t)gridDim.x * kReduceThreads) {
+        const S v = src[p];
+        if constexpr (storage_traits<D>::complex) {
+            D d;
+            if constexpr (storage_traits<S>::complex) {
+                d.x = (R)v.x;
+                d.y = (R)v.y;
+            } else {
+                d.x = (R)v;
+                d.y = (R)0;
+            }
+            dst[p] = d;
+        } else if constexpr (storage_traits<S>::complex) {
+            dst[p] = (R)v.x;
+        } else {
+            dst[p] = (R)v;
+        }
+    }
+}
+
+hipError_t launch_convert(Prec to, Prec from, void *dst, const void *src, int64_t elems, hipStream_t stream)
+{
+    int64_t blocks = (elems + kReduceThreads - 1) / kReduceThreads;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    const dim3 grid((unsigned)blocks), block(kReduceThreads);
+#define GP_CONV(DT, ST)                                                                                       \
+    hipLaunchKernelGGL((convert_kernel<DT, ST>), grid, block, 0, stream, static_cast<DT *>(dst),              \
+                       static_cast<const ST *>(src), elems);                                                  \
+    return hipGetLastError();
+    if (to == PREC_C128 && from == PREC_C64) { GP_CONV(double2, float2) }
+    if (to == PREC_C64 && from == PREC_C128) { GP_CONV(float2, double2) }
+    if (to == PREC_R64 && from == PREC_R32) { GP_CONV(double, float) }
+    if (to == PREC_R32 && from == PREC_R64) { GP_CONV(float, double) }
+    if (to == PREC_R32 && from == PREC_C64) { GP_CONV(float, float2) }
+    if (to == PREC_C64 && from == PREC_R32) { GP_CONV(float2, float) }
+    if (to == PREC_R64 && from == PREC_C128) { GP_CONV(double, double2) }
+    if (to == PREC_C128 && from == PREC_R64) { GP_CONV(double2, double) }
+#undef GP_CONV
+    return hipErrorInvalidValue;
+}
+
 int obs_num_blocks(int nx, int ny)
 {
     return ((nx + kObsX - 1) / kObsX) * ((ny + kObsY - 1) / kObsY);

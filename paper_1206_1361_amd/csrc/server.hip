@@ -116,6 +116,7 @@ struct Pending {
     gp_request r;
     double t_submit;
     int passed = 0;
+    bool auto_real = false;   // complex host buffers, real storage (GP_SERVER_REAL_AUTO)
 };
 
 struct Live {
@@ -131,6 +132,7 @@ struct Live {
     bool fresh = true;     // its step-0 observables are pending (imaginary time)
     bool due = false;      // an event at the end of this round
     bool done = false;
+    bool auto_real = false;
 };
 
 struct SClass : ClassShape {
@@ -173,6 +175,8 @@ struct gp_server {
     std::chrono::steady_clock::time_point t0;
     hipStream_t stream = nullptr;
     unsigned char *d_arena = nullptr;
+    unsigned char *d_stage = nullptr;   // engine thread: complex staging of GP_SERVER_REAL_AUTO requests
+    size_t stage_bytes = 0;
 
     // guarded by mu
     std::mutex mu;
@@ -226,6 +230,7 @@ void free_graph(gp_server *S)
 void release(gp_server *S)
 {
     free_graph(S);
+    if (S->d_stage) (void)hipFree(S->d_stage);
     for (SClass &c : S->cls) {
         if (c.d_list) (void)hipFree(c.d_list);
         if (c.d_due) (void)hipFree(c.d_due);
@@ -287,6 +292,19 @@ hipError_t class_of(gp_server *S, const int64_t grid[3], bool real, gp_dtype dt,
 }
 
 // Copies a request in: tables, kernel arguments and psi (engine thread).
+// Grows the complex staging buffer to at least n bytes (engine thread; the
+// stream has no pending use of it: every use ends with a synchronisation).
+hipError_t ensure_stage(gp_server *S, size_t n)
+{
+    if (S->stage_bytes >= n) return hipSuccess;
+    if (S->d_stage) (void)hipFree(S->d_stage);
+    S->d_stage = nullptr;
+    S->stage_bytes = 0;
+    hipError_t e = hipMalloc((void **)&S->d_stage, n);
+    if (e == hipSuccess) S->stage_bytes = n;
+    return e;
+}
+
 template <typename A>
 hipError_t stage_solve(gp_server *S, Live &L, const SClass &c, const Footprint &f)
 {
@@ -323,7 +341,18 @@ hipError_t stage_solve(gp_server *S, Live &L, const SClass &c, const Footprint &
     };
     hipError_t e = hipSuccess;
     for (const Up &u : ups)
-        if (e == hipSuccess) e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, S->stream);
+        if (e == hipSuccess && !(L.auto_real && u.dst == blk))
+            e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, S->stream);
+    if (e == hipSuccess && L.auto_real) {
+        // the complex state through the staging buffer, its real part to the slot
+        e = ensure_stage(S, storage_bytes(S->dtype) * (size_t)L.d.elems);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S->d_stage, L.r.psi_in, storage_bytes(S->dtype) * (size_t)L.d.elems,
+                               hipMemcpyHostToDevice, S->stream);
+        if (e == hipSuccess)
+            e = gpssc::launch_convert(static_cast<gpssc::Prec>(L.dt), static_cast<gpssc::Prec>(S->dtype), blk,
+                                      S->d_stage, L.d.elems, S->stream);
+    }
     // the tables vector is pageable and local: finish its copy before it goes
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     return e;
@@ -408,8 +437,19 @@ void finish(gp_server *S, Live &L, gp_status status, const gp_obs &obs, bool con
     L.done = true;
     // psi out, then the memory is free
     const double tc = now_since(S->t0);
-    hipError_t e = hipMemcpyAsync(L.r.psi_out, S->d_arena + L.off, storage_bytes(L.dt) * (size_t)L.d.elems,
-                                  hipMemcpyDeviceToHost, S->stream);
+    hipError_t e = hipSuccess;
+    if (L.auto_real) {   // back to complex through the staging buffer
+        e = ensure_stage(S, storage_bytes(S->dtype) * (size_t)L.d.elems);
+        if (e == hipSuccess)
+            e = gpssc::launch_convert(static_cast<gpssc::Prec>(S->dtype), static_cast<gpssc::Prec>(L.dt),
+                                      S->d_stage, S->d_arena + L.off, L.d.elems, S->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L.r.psi_out, S->d_stage, storage_bytes(S->dtype) * (size_t)L.d.elems,
+                               hipMemcpyDeviceToHost, S->stream);
+    } else {
+        e = hipMemcpyAsync(L.r.psi_out, S->d_arena + L.off, storage_bytes(L.dt) * (size_t)L.d.elems,
+                           hipMemcpyDeviceToHost, S->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess && r.status == GP_OK) r.status = GP_ERR_DEVICE;
     S->acc_out += now_since(S->t0) - tc;
@@ -507,6 +547,7 @@ bool round_once(gp_server *S)
         Live L;
         L.id = p.id;
         L.r = p.r;
+        L.auto_real = p.auto_real;
         L.t_submit = p.t_submit;
         L.t_admit = tnow;
         L.off = ad.off;
@@ -680,7 +721,7 @@ gp_status gp_server_create(gp_dtype dtype, uint64_t hbm_budget, int max_slots, i
     if (max_slots < 1 || max_slots > kMaxSlots) return fail(GP_ERR_INVALID, "max_slots must be in 1..4096");
     if (check_every < 1) return fail(GP_ERR_INVALID, "check_every must be >= 1");
     if (hbm_budget < kAlign) return fail(GP_ERR_INVALID, "hbm_budget is too small");
-    if (flags & ~GP_SERVER_GRAPH) return fail(GP_ERR_INVALID, "unknown flags");
+    if (flags & ~(GP_SERVER_GRAPH | GP_SERVER_REAL_AUTO)) return fail(GP_ERR_INVALID, "unknown flags");
     gp_server *S = new (std::nothrow) gp_server();
     if (!S) return fail(GP_ERR_NOMEM, "host allocation failed");
     S->dtype = dtype;
@@ -781,7 +822,27 @@ gp_status gp_server_submit(gp_server *S, const gp_request *r, uint64_t *id)
         return fail(GP_ERR_INVALID, "a server with real storage takes imaginary-time requests only");
     if (r->real_state && (r->mode != GP_MODE_IMAG || S->dtype == GP_C64_F64))
         return fail(GP_ERR_INVALID, "real_state needs an imaginary-time request on a GP_C128 or GP_C64 server");
-    const gp_dtype rdt = request_dtype(S->dtype, *r);
+    gp_request rq = *r;
+    bool auto_real = false;
+    if ((S->flags & GP_SERVER_REAL_AUTO) && r->mode == GP_MODE_IMAG && !r->real_state &&
+        (S->dtype == GP_C64 || S->dtype == GP_C128)) {
+        // an imaginary-time state with no imaginary part stays real: every
+        // imaginary-time operator is real
+        const int64_t n = r->grid[0] * r->grid[1] * r->grid[2];
+        bool zero = true;
+        if (S->dtype == GP_C64) {
+            const float *v = static_cast<const float *>(r->psi_in);
+            for (int64_t q = 0; q < n && zero; ++q) zero = v[2 * q + 1] == 0.0f;
+        } else {
+            const double *v = static_cast<const double *>(r->psi_in);
+            for (int64_t q = 0; q < n && zero; ++q) zero = v[2 * q + 1] == 0.0;
+        }
+        if (zero) {
+            auto_real = true;
+            rq.real_state = 1;
+        }
+    }
+    const gp_dtype rdt = request_dtype(S->dtype, rq);
     if (!grid_supported(r->grid, rdt)) return fail(GP_ERR_UNSUPPORTED, "grid line too long (each <= 1024)");
     const size_t need = gp_server_request_bytes(r->grid, rdt, r->mode);
     std::lock_guard<std::mutex> lk(S->mu);
@@ -792,7 +853,8 @@ gp_status gp_server_submit(gp_server *S, const gp_request *r, uint64_t *id)
                                       std::to_string(S->arena.size));
     Pending p;
     p.id = S->next_id++;
-    p.r = *r;
+    p.r = rq;
+    p.auto_real = auto_real;
     p.t_submit = now_since(S->t0);
     S->queue.push_back(p);
     ++S->st.submitted;

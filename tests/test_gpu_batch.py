@@ -223,3 +223,37 @@ def test_batch_binding_checks():
         with pytest.raises(ValueError):
             b.bind([initial(specs[0], 1, "c64"), initial(specs[1], 2, "c64")])
         assert "2 solves" in b.describe()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "r32"])
+def test_fp32_batch_with_fp64_finish_meets_the_fp32_bounds(dtype):
+    """Eight imaginary-time solves stopped at |delta mu| < 1e-8 in float
+    storage with the FP64 finishing phase (GP_BATCH_FINISH_F64), against the
+    oracle stepped in FP64 from the same (float-rounded) starts to each
+    solve's step count: mu within 1e-7 and psi within 1e-5, the bounds for
+    the FP32 form."""
+    rng = np.random.default_rng(12)
+    shapes = [(16, 16, 16), (20, 18, 16), (14, 20, 18), (18, 14, 20)]
+    specs = [dict(grid=shapes[i % 4], dx=0.6, dt=0.1 * 0.36, trap=tuple(rng.uniform(1.0, 3.0, 3)),
+                  g=float(np.exp(rng.uniform(0.0, np.log(100.0))))) for i in range(8)]
+    real = dtype == "r32"
+    tdt = torch.float32 if real else torch.complex64
+    starts = []
+    for sp in specs:
+        psi = inputs.gaussian(sp["grid"], (sp["dx"],) * 3, sp["trap"])
+        psi = psi.real.astype(np.float32) if real else psi.astype(np.complex64)
+        starts.append(psi)
+    psis = [torch.from_numpy(p.copy()).to(tdt).cuda() for p in starts]
+    with gp.Batch(specs, mode="imag", dtype=dtype, finish_f64=True) as b:
+        b.bind(psis)
+        obs, steps, conv = b.solve_imag(tol=1e-8, check_every=10, max_steps=20000)
+    assert all(conv), (steps, conv)
+    for i, sp in enumerate(specs):
+        dx3 = (sp["dx"],) * 3
+        ref = starts[i].astype(np.complex128)
+        oracle.step(ref, dx3, sp["dt"], sp["trap"], sp["g"], oracle.IMAG, steps[i])
+        robs = oracle.observables(ref, dx3, sp["trap"], sp["g"])
+        got = psis[i].cpu().numpy().astype(np.complex128)
+        print(f"solve {i} {sp['grid']}: {steps[i]} steps, mu {obs[i]['mu']:.9f} oracle {robs['mu']:.9f}")
+        assert abs(obs[i]["mu"] - robs["mu"]) <= 1e-7 * abs(robs["mu"]), i
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), i

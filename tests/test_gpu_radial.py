@@ -10,7 +10,20 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_1206_1361_amd as gp  # noqa: E402
 
-TOL = {"c128": (1e-12, 1e-12), "c64": (1e-5, 3e-6), "r64": (1e-12, 1e-12), "r32": (1e-5, 3e-6)}
+# (psi, mu and energy) relative to the oracle.  Float storage on these grids
+# of at most 26000 points: mu and E within 1e-6 (the per-store rounding is
+# not averaged below 1e-7 on so few points; measured at most 3.0e-7).  The
+# norm: 2e-7 in imaginary time (renormalised to within a float ulp), and in
+# real time 2 (3n + 1) 2^-24 after n steps: the FP32 Crank-Nicolson and
+# phase factors are unitary only to about 2^-24 each, and each store can
+# move |psi|^2 by 2 x 2^-24 (measured at most 5.5e-7 at n = 6).
+TOL = {"c128": (1e-12, 1e-12), "c64": (1e-5, 1e-6), "r64": (1e-12, 1e-12), "r32": (1e-5, 1e-6)}
+
+
+def norm_tol(dtype, mode, nsteps):
+    if dtype in ("c128", "r64"):
+        return 1e-12
+    return 2 * (3 * nsteps + 1) * 2.0 ** -24 if mode == "real" else 2e-7
 TORCH = {"c128": torch.complex128, "c64": torch.complex64, "r64": torch.float64, "r32": torch.float32}
 MODE_DTYPES = [("imag", d) for d in ("c128", "c64", "r64", "r32")] + [("real", d) for d in ("c128", "c64")]
 CASES = [("circular", (1, 1, 1)), ("circular", (37, 1, 1)), ("circular", (200, 1, 1)), ("circular", (1024, 1, 1)),
@@ -42,6 +55,8 @@ def test_radial_step_matches_oracle(geom, grid, mode, dtype):
     g, steps = 30.0, 5
     real_state = dtype in ("r64", "r32")
     psi0 = start(geom, grid, dx, real_state, sum(grid))
+    if dtype in ("c64", "r32"):   # the oracle starts from the values the GPU holds
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
     ref = psi0.copy()
     oracle.radial_step(ref, geom, dx, dt, OMEGA, g, oracle.IMAG if mode == "imag" else oracle.REAL, steps)
     robs = oracle.radial_observables(ref, geom, dx, OMEGA, g)
@@ -53,7 +68,8 @@ def test_radial_step_matches_oracle(geom, grid, mode, dtype):
     got = t.cpu().numpy().astype(np.complex128)
     tpsi, tobs = TOL[dtype]
     assert rel(got, ref) <= tpsi
-    for k in ("norm", "mu", "energy", "rms_x", "rms_r"):
+    assert abs(obs["norm"] - robs["norm"]) <= norm_tol(dtype, mode, steps) * robs["norm"]
+    for k in ("mu", "energy", "rms_x", "rms_r"):
         assert abs(obs[k] - robs[k]) <= tobs * abs(robs[k]), k
     if geom == "axial":
         assert abs(obs["rms_y"] - robs["rms_y"]) <= tobs * robs["rms_y"]

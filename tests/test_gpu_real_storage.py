@@ -46,10 +46,12 @@ def test_real_step_is_bitwise_the_complex_step(dtype, grid):
         assert orr[k] == oc[k], k
 
 
-@pytest.mark.parametrize("dtype,tpsi,tmu", [("r64", 1e-12, 1e-12), ("r32", 1e-5, 3e-6)])
+@pytest.mark.parametrize("dtype,tpsi,tmu", [("r64", 1e-12, 1e-12), ("r32", 1e-5, 1e-7)])
 def test_real_storage_matches_oracle(dtype, tpsi, tmu):
     w = inputs.SMALL_IMAG
     psi0 = inputs.initial_state(w).real.copy()
+    if dtype == "r32":   # the oracle starts from the values the GPU holds
+        psi0 = psi0.astype(np.float32).astype(np.float64)
     ref = psi0.astype(np.complex128)
     oracle.step(ref, w.dx, w.dt, w.omega, w.g, oracle.IMAG, w.steps)
     robs = oracle.observables(ref, w.dx, w.omega, w.g)
@@ -60,8 +62,9 @@ def test_real_storage_matches_oracle(dtype, tpsi, tmu):
     got = t.cpu().numpy().astype(np.float64)
     assert np.max(np.abs(ref.imag)) == 0.0
     assert np.max(np.abs(got - ref.real)) <= tpsi * np.max(np.abs(ref.real))
-    for k in ("mu", "energy", "norm"):
+    for k in ("mu", "energy"):
         assert abs(obs[k] - robs[k]) <= tmu * abs(robs[k]), k
+    assert abs(obs["norm"] - robs["norm"]) <= (2e-7 if dtype == "r32" else 1e-12) * robs["norm"]
 
 
 @pytest.mark.parametrize("dtype", ["r64", "r32"])

@@ -231,3 +231,80 @@ def test_real_states_on_real_storage(dtype):
         with pytest.raises(gp.GPInvalid):
             srv.submit(np.ascontiguousarray(bad["psi"].real).astype(npr), dx=bad["dx"], dt=bad["dt"],
                        trap=bad["trap"], g=bad["g"], mode="real", steps=10)
+
+
+MODES_ORACLE = {"imag": 0, "real": 1}
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_served_results_match_the_oracle(dtype):
+    """Mixed requests (ground states and a real-time quench) served together,
+    each against the oracle stepped in check_every chunks to the served step
+    count: psi and mu within the dtype's bounds (complex128 1e-12; complex64
+    psi 1e-5, mu 1e-7 on these grids of at least 32^3 points)."""
+    import oracle
+
+    rng = np.random.default_rng(17)
+    npd = np.complex64 if dtype == "c64" else np.complex128
+    shapes = [(32, 32, 32), (40, 34, 30), (36, 40, 32), (32, 36, 40)]
+    reqs = []
+    for i in range(4):
+        grid = shapes[i]
+        trap = tuple(float(v) for v in rng.uniform(0.8, 2.5, 3))
+        real = i == 3
+        dx = 0.3
+        psi = inputs.smooth_random_state(grid, (dx,) * 3, trap, seed=40 + i).astype(npd)
+        reqs.append(dict(psi=psi, dx=dx, dt=(0.005 if real else 0.1) * dx * dx, trap=trap,
+                         g=float(rng.uniform(5.0, 200.0)), mode="real" if real else "imag",
+                         steps=150 if real else 120, tol=0.0))
+    starts = [rq["psi"].copy() for rq in reqs]
+    with gp.Server(dtype=dtype, hbm_budget=256 << 20, max_slots=8, check_every=K) as srv:
+        for i, rq in enumerate(reqs):
+            submit(srv, rq, i)
+        got = collect(srv, len(reqs))
+    tpsi, tmu = (1e-12, 1e-12) if dtype == "c128" else (1e-5, 1e-7)
+    for i, rq in enumerate(reqs):
+        r = got[i]
+        assert r["status"] == 0 and r["steps"] == rq["steps"], (i, r["status"], r["steps"])
+        dx3 = (rq["dx"],) * 3
+        ref = starts[i].astype(np.complex128)
+        for _ in range(rq["steps"] // K):
+            oracle.step(ref, dx3, rq["dt"], rq["trap"], rq["g"], MODES_ORACLE[rq["mode"]], K)
+        robs = oracle.observables(ref, dx3, rq["trap"], rq["g"])
+        out = r["psi"].astype(np.complex128)
+        err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+        dmu = abs(r["obs"]["mu"] - robs["mu"]) / abs(robs["mu"])
+        print(f"request {i} {rq['mode']} {dtype}: psi {err:.2e} mu {dmu:.2e}")
+        assert err <= tpsi, i
+        assert dmu <= tmu, i
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_real_starts_detected_and_run_on_real_storage(dtype):
+    """GP_SERVER_REAL_AUTO: a ground-state request with a complex start whose
+    imaginary parts are all zero runs on real storage -- bitwise the result
+    of sending the real array (real_state), written back with zero imaginary
+    parts -- while a complex start and a real-time request are unaffected."""
+    npd = np.complex64 if dtype == "c64" else np.complex128
+    npr = np.float32 if dtype == "c64" else np.float64
+    grid, dx, trap = (40, 32, 24), 0.3, (1.0, 1.4, 1.9)
+    base = inputs.gaussian(grid, (dx,) * 3, trap)
+    cplx = inputs.smooth_random_state(grid, (dx,) * 3, trap, seed=5).astype(npd)
+    args = dict(dx=dx, dt=0.1 * dx * dx, trap=trap, g=40.0, mode="imag", steps=200, tol=0.0)
+    with gp.Server(dtype=dtype, hbm_budget=256 << 20, max_slots=8, check_every=K, real_auto=True) as auto, \
+            gp.Server(dtype=dtype, hbm_budget=256 << 20, max_slots=8, check_every=K) as plain:
+        auto.submit(base.astype(npd), tag=0, **args)
+        auto.submit(cplx.copy(), tag=1, **args)
+        auto.submit(base.astype(npd), tag=2, **dict(args, mode="real", dt=0.005 * dx * dx, steps=50))
+        plain.submit(base.real.astype(npr), tag=0, **args)        # real_state: a real array
+        plain.submit(cplx.copy(), tag=1, **args)
+        plain.submit(base.astype(npd), tag=2, **dict(args, mode="real", dt=0.005 * dx * dx, steps=50))
+        a = collect(auto, 3)
+        p = collect(plain, 3)
+    assert a[0]["psi"].dtype == npd and p[0]["psi"].dtype == npr
+    assert np.array_equal(a[0]["psi"].real, p[0]["psi"])
+    assert not np.any(a[0]["psi"].imag)
+    assert a[0]["obs"]["mu"] == p[0]["obs"]["mu"]
+    for t in (1, 2):
+        assert np.array_equal(a[t]["psi"], p[t]["psi"]), t
+        assert a[t]["obs"]["mu"] == p[t]["obs"]["mu"], t

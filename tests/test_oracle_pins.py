@@ -10,6 +10,7 @@ dropped ghost term, a wrong sign of i, a wrong stride, a transposed axis, a
 missing 1/2) fails at least one of them.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -371,3 +372,24 @@ def test_thread_count_does_not_change_results(oracle_lib):
         oracle.set_threads(before)
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
+
+
+def test_small_imaginary_time_record():
+    """The oracle still gives the recorded mu, E and rms sizes of the 32^3
+    imaginary-time workload (tests/golden/small_imag_oracle.json, written by
+    make_small_imag.py from the oracle alone).  The paper prints no numbers
+    for it, so the record is parity unpinned beyond the oracle's own
+    mathematical checks; it guards the oracle against regressions."""
+    import json
+
+    from paper_1206_1361_amd import inputs
+
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "small_imag_oracle.json")))
+    w = inputs.SMALL_IMAG
+    assert rec["steps"] == w.steps
+    psi = inputs.initial_state(w)
+    oracle.step(psi, w.dx, w.dt, w.omega, w.g, oracle.IMAG, w.steps)
+    obs = oracle.observables(psi, w.dx, w.omega, w.g)
+    for k, want in rec["observables"].items():
+        assert abs(obs[k] - want) <= 1e-13 * max(abs(want), 1e-3), k
