@@ -13,20 +13,27 @@ second over K timed steps with psi resident in HBM; the `fp32` object holds
 the complex64 run.  `roofline` is the dominant kernel's algorithmic bytes
 (one read + one write of psi per launch) over its mean duration from HIP
 events recorded on the plan's stream inside the timed region, against the
-8 TB/s HBM3E peak.  `cpu_baseline` is the FP64 oracle timed on this host's
-cores over a bounded sample of the same workload.  `latency` is the
-end-to-end time of the small imaginary-time solve (32^3, 200 steps),
-upload to observables on the host, p50/p99 over repeated solves.  `batch`
-runs 256 uneven imaginary-time ground-state solves (grids 48^3 to 160^3,
-dx 0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between
-checks 10 steps apart) as one complex64 batch and, for comparison, one by
-one on complex128 plans, with the complex64 error at equal step counts.
-`cache_resident` times the 240x200x160 quench grid, whose state fits the
-Infinity Cache (effective rates, not HBM figures).  `serve` drives the
-request server with Poisson arrivals at 50/s of mixed
-ground-state and real-time requests (64^3 to 160x128x96) for a few seconds
-and reports p50/p99 latency and throughput (python -m
-paper_1206_1361_amd.serve runs the full 60 s).
+8 TB/s HBM3E peak; `step_hbm_frac` prices the whole step at three such
+passes, `step_floor_frac` at the strict floor of one.  `cpu_baseline` is
+the FP64 oracle timed on this host's cores (all threads, and one thread)
+over a bounded sample of the same workload.  Further objects:
+`fp32_error`: complex64 (FP32 and FP64 arithmetic) against complex128 after
+  500 steps of the same run (norm, energy, mu, max |psi| error);
+`quench`: the 240x200x160 workload -- ground state at g = 22 relaxed on the
+  GPU, 1e-3 phase noise, quench to g = 11, 1000 steps in complex128 and
+  complex64 with norm drift and rms(t) every 10 steps (the state fits the
+  Infinity Cache: effective rates);
+`small`: the 32^3 imaginary-time workload's mu, E and rms sizes on the GPU
+  and from the oracle, with the oracle's time to finish;
+`latency`: end-to-end time of that solve (upload to observables on the
+  host), p50/p99 over repeated solves;
+`batch`: 256 uneven imaginary-time ground states (grids 48^3 to 160^3, dx
+  0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between checks
+  10 steps apart) in several storage forms, against the same solves one by
+  one on complex128 plans, with each form's error;
+`serve`, `serve_c128`: the request server under Poisson arrivals at 50/s of
+  mixed ground-state and real-time requests (64^3 to 160x128x96) for 60 s,
+  p50/p99 latency and throughput.
 """
 from __future__ import annotations
 
@@ -111,6 +118,7 @@ def run_dtype(gp, torch, w, psi_host, dtype: str, steps: int, warmup: int) -> di
             "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic}
     step_bytes = 3 * 2 * points * bpp
+    floor_bytes = 2 * points * bpp          # one read and one write of psi per step
     return {
         "value": points * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
@@ -118,26 +126,59 @@ def run_dtype(gp, torch, w, psi_host, dtype: str, steps: int, warmup: int) -> di
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "GB/s": round(v["gbs"], 1),
                         "frac": round(v["gbs"] / HBM_PEAK_GBS, 4)} for k, v in kernels.items()},
         "step_hbm_frac": round(step_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_floor_frac": round(floor_bytes / (elapsed / steps) / 1e9 / HBM_PEAK_GBS, 4),
         "norm_drift": abs(n1 - n0),
     }
 
 
-def cache_resident(gp, torch, steps: int) -> dict:
-    """The 240x200x160 quench grid (after the g 22 -> 11 quench), complex128
-    and complex64.  Its 117 MiB (59 MiB) fit the 256 MB Infinity Cache, so
-    the sweeps' rates are effective ones, not HBM figures."""
+def quench(gp, torch, steps: int, every: int = 10, relax_tol: float = 1e-10, relax_cap: int = 40000) -> dict:
+    """The real-time quench workload (240x200x160, dx 0.1, trap (0.5, 1,
+    1.5)): its ground state at g = 22 is relaxed in imaginary time on the GPU
+    (real float64 storage, dt = 0.1 dx^2, from the Thomas-Fermi profile,
+    stopped when mu moves by less than relax_tol over 100 steps), multiplied
+    by the seeded 1e-3 phase noise, and then evolved `steps` real-time steps
+    at g = 11 in complex128 and in complex64.  Reports the throughput of an
+    uninterrupted run and, from a second run with observables every `every`
+    steps, the norm drift and rms(t).  The 117 MiB (59 MiB) state fits the
+    256 MB Infinity Cache, so the sweeps' rates are effective ones, not HBM
+    figures."""
     from paper_1206_1361_amd import inputs
 
     w = inputs.QUENCH
-    psi_host = inputs.initial_state(w)
-    out = {"workload": w.name, "grid": list(w.grid), "steps": steps,
+    dt_imag = 0.1 * w.dx[0] ** 2
+    gs = torch.from_numpy(inputs.quench_relaxation_start(w).real.copy()).cuda()
+    t0 = time.perf_counter()
+    with gp.Plan(w.grid, w.dx, dt_imag, *w.omega, w.g, mode="imag", dtype="r64") as p:
+        last = p.observables(gs)["mu"]
+        relaxed, conv = 0, False
+        while relaxed < relax_cap:
+            p.step(gs, 100)
+            relaxed += 100
+            obs = p.observables(gs)
+            if abs(obs["mu"] - last) < relax_tol:
+                conv = True
+                break
+            last = obs["mu"]
+    t_relax = time.perf_counter() - t0
+    log(f"[bench] quench: ground state at g = {w.g:g} after {relaxed} imaginary-time steps "
+        f"({t_relax:.1f} s), mu {obs['mu']:.9f}")
+    psi0 = inputs.phase_noise(gs.cpu().numpy().astype(np.complex128), 1e-3, 2)
+    del gs
+    out = {"workload": w.name, "grid": list(w.grid), "dx": w.dx[0], "dt": w.dt, "trap": list(w.omega),
+           "g_ground_state": w.g, "g_after": w.g_after, "steps": steps,
+           "ground_state": {"storage": "float64", "dt": dt_imag, "steps": relaxed, "converged": conv,
+                            "stop": f"|dmu| < {relax_tol:g} over 100 steps", "mu": obs["mu"],
+                            "energy": obs["energy"], "seconds": round(t_relax, 2)},
+           "start": "ground state x exp(i theta), theta ~ U(-1e-3, 1e-3), default_rng(2)",
            "note": "the state fits the 256 MB Infinity Cache: effective rates, not HBM bandwidth"}
+    traj = {}
     for dtype in ("c128", "c64"):
-        psi = torch.from_numpy(psi_host).to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
         bpp = 16 if dtype == "c128" else 8
-        with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g_after, mode=w.mode, dtype=dtype) as plan:
-            plan.step(psi, 10)
-            plan.sync()
+        psi = torch.from_numpy(psi0).to(tdt).cuda()
+        with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g_after, mode="real", dtype=dtype) as plan:
+            plan.step(psi, 1)            # warm the kernels (on a copy below)
+            psi.copy_(torch.from_numpy(psi0).to(tdt))
             plan.profile(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -146,18 +187,99 @@ def cache_resident(gp, torch, steps: int) -> dict:
             t1 = time.perf_counter()
             prof = plan.profile_read()
             plan.profile(False)
+            psi.copy_(torch.from_numpy(psi0).to(tdt))
+            rows = []
+            o = plan.observables(psi)
+            rows.append([0, o["norm"], o["rms_x"], o["rms_y"], o["rms_z"], o["energy"]])
+            for k in range(every, steps + 1, every):
+                plan.step(psi, every)
+                o = plan.observables(psi)
+                rows.append([k, o["norm"], o["rms_x"], o["rms_y"], o["rms_z"], o["energy"]])
+        r = np.array(rows)
+        traj[dtype] = r
         alg = 2 * w.points * bpp
-        out[dtype] = {"value": w.points * steps / (t1 - t0), "ms_per_step": (t1 - t0) / steps * 1e3,
-                      "effective_GB/s": {k: round(alg / (ms / n * 1e-3) / 1e9, 1)
-                                         for k, (ms, n) in prof.items() if n}}
+        out[dtype] = {
+            "value": w.points * steps / (t1 - t0), "ms_per_step": (t1 - t0) / steps * 1e3,
+            "effective_GB/s": {k: round(alg / (ms / n * 1e-3) / 1e9, 1) for k, (ms, n) in prof.items() if n},
+            "norm_drift_max": float(np.max(np.abs(r[:, 1] - r[0, 1]))),
+            "energy_drift_max_rel": float(np.max(np.abs(r[:, 5] - r[0, 5])) / abs(r[0, 5])),
+            "rms_t": {"every_steps": every, "columns": ["step", "rms_x", "rms_y", "rms_z"],
+                      "rows": [[int(a), round(b, 8), round(c, 8), round(d, 8)] for a, b, c, d in r[:, [0, 2, 3, 4]]]},
+        }
+        log(f"[bench] quench {dtype}: {out[dtype]['ms_per_step']:.3f} ms/step, norm drift "
+            f"{out[dtype]['norm_drift_max']:.2e}")
         del psi
+    d = np.abs(traj["c64"][:, 2:5] - traj["c128"][:, 2:5]) / traj["c128"][:, 2:5]
+    out["c64_vs_c128_rms_rel_max"] = float(np.max(d))
     return out
 
 
-def cpu_baseline(w, psi_host, budget_s: float) -> dict:
+def large_fp32_error(gp, torch, w, psi_host, steps: int) -> dict:
+    """The FP32-storage forms against complex128 after `steps` real-time
+    steps of the large grid, all from the same start: relative error of the
+    norm and the energy, and max|psi - psi_c128| / max|psi_c128|.  The
+    complex128 path is itself held to the FP64 oracle at 1e-12 by the GPU
+    parity tests (one step over the whole grid; every 4th z plane after
+    three)."""
+    res, ref_obs = {}, None
+    ref = torch.from_numpy(psi_host).cuda()
+    with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype="c128") as p:
+        p.step(ref, steps)
+        ref_obs = p.observables(ref)
+    scale = ref.abs().max().item()
+    for dtype, arith in (("c64", "f32"), ("c64_f64", "f64")):
+        psi = torch.from_numpy(psi_host).to(torch.complex64).cuda()
+        with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype=dtype) as p:
+            p.step(psi, steps)
+            o = p.observables(psi)
+        err = 0.0
+        for k in range(0, w.grid[2], 32):      # in slabs: no grid-sized complex128 temporary
+            err = max(err, (psi[k:k + 32].to(torch.complex128) - ref[k:k + 32]).abs().max().item())
+        res[dtype] = {"storage": "complex64", "arithmetic": arith,
+                      "norm_rel": abs(o["norm"] - ref_obs["norm"]) / ref_obs["norm"],
+                      "energy_rel": abs(o["energy"] - ref_obs["energy"]) / abs(ref_obs["energy"]),
+                      "mu_rel": abs(o["mu"] - ref_obs["mu"]) / abs(ref_obs["mu"]),
+                      "psi_rel": err / scale}
+        del psi
+    del ref
+    return {"workload": w.name, "steps": steps, "reference": "complex128 on the GPU (held to the FP64 oracle "
+            "at 1e-12 by the parity tests)", **res}
+
+
+def small_report(gp, torch) -> dict:
+    """The smallest workload (32^3 imaginary time, 200 steps): mu, E, rms of
+    the complex128 GPU run and of the FP64 oracle, and the oracle's time to
+    finish on 1 thread and on all host threads."""
     import oracle
 
-    cores = oracle.get_threads()
+    from paper_1206_1361_amd import inputs
+
+    w = inputs.SMALL_IMAG
+    psi0 = inputs.initial_state(w)
+    psi = torch.from_numpy(psi0).cuda()
+    with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode="imag", dtype="c128") as p:
+        p.step(psi, w.steps)
+        go = p.observables(psi)
+    allt = oracle.get_threads()
+    timing = {}
+    for nt in (1, allt):
+        oracle.set_threads(nt)
+        ref = psi0.copy()
+        t0 = time.perf_counter()
+        oracle.step(ref, w.dx, w.dt, w.omega, w.g, oracle.IMAG, w.steps)
+        timing[nt] = time.perf_counter() - t0
+    oracle.set_threads(allt)
+    ro = oracle.observables(ref, w.dx, w.omega, w.g)
+    keys = ("mu", "energy", "rms_x", "rms_y", "rms_z", "rms_r", "norm")
+    return {"workload": w.name, "steps": w.steps, "gpu_c128": {k: go[k] for k in keys},
+            "oracle": {k: ro[k] for k in keys},
+            "gpu_vs_oracle_rel_max": max(abs(go[k] - ro[k]) / abs(ro[k]) for k in keys),
+            "oracle_seconds": {"threads_1": round(timing[1], 4), f"threads_{allt}": round(timing[allt], 4)}}
+
+
+def _oracle_rate(w, psi_host, budget_s: float):
+    import oracle
+
     psi = psi_host.copy()
     mode = oracle.REAL if w.mode == "real" else oracle.IMAG
     t0 = time.perf_counter()
@@ -168,10 +290,24 @@ def cpu_baseline(w, psi_host, budget_s: float) -> dict:
     if more:
         oracle.step(psi, w.dx, w.dt, w.omega, w.g, mode, more)
     total = one + (time.perf_counter() - t1)
-    n = 1 + more
-    return {"value": w.points * n / total, "unit": UNIT, "cores": cores, "kind": "oracle",
+    return w.points * (1 + more) / total, 1 + more, total
+
+
+def cpu_baseline(w, psi_host, budget_s: float) -> dict:
+    """The FP64 oracle on all host threads and on one, each over a bounded
+    sample of the workload's steps (about budget_s / 2 seconds each)."""
+    import oracle
+
+    cores = oracle.get_threads()
+    v, n, total = _oracle_rate(w, psi_host, budget_s / 2)
+    oracle.set_threads(1)
+    v1, n1, total1 = _oracle_rate(w, psi_host, budget_s / 2)
+    oracle.set_threads(cores)
+    return {"value": v, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{n} of the {w.steps} real-time steps of the {w.name} grid, complex128, "
-                      f"{total:.1f} s on {cores} threads"}
+                      f"{total:.1f} s on {cores} threads",
+            "one_thread": {"value": v1, "unit": UNIT, "cores": 1,
+                           "sample": f"{n1} steps, {total1:.1f} s on 1 thread"}}
 
 
 def latency(gp, torch, repeats: int) -> dict:
@@ -213,10 +349,12 @@ def _solve_plan(gp, torch, sp, psi, dtype, tol, check_every, max_steps):
 
 
 BATCH_FORMS = {
-    # name: (storage dtype, torch element type name, arithmetic)
-    "c64": ("complex64", "f32"),
-    "r64": ("float64", "f64"),
-    "r32": ("float32", "f32"),
+    # name: (library dtype, torch storage type, arithmetic, FP64 finishing phase)
+    "c64": ("c64", "complex64", "f32", False),
+    "c64+c128": ("c64", "complex64", "f32, finished in f64 on complex128", True),
+    "r64": ("r64", "float64", "f64", False),
+    "r32": ("r32", "float32", "f32", False),
+    "r32+r64": ("r32", "float32", "f32, finished in f64 on float64", True),
 }
 
 
@@ -253,14 +391,14 @@ def batch_bench(gp, torch, nsolves: int, tol: float, check_every: int, max_steps
     log(f"[bench] batch: complex128 one by one {t64:.2f} s, {sum(conv64)}/{nsolves} converged")
 
     forms = {}
-    for name, (tname, arith) in BATCH_FORMS.items():
+    for name, (ldt, tname, arith, finish) in BATCH_FORMS.items():
         tdt = getattr(torch, tname)
         log(f"[bench] batch: {nsolves} solves as one {name} batch {classes}")
         real = not tdt.is_complex
         psis = [torch.from_numpy(start(sp).real.copy() if real else start(sp)).to(tdt).cuda() for sp in specs]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        with gp.Batch(specs, mode="imag", dtype=name, graph=True, tune=True) as b:
+        with gp.Batch(specs, mode="imag", dtype=ldt, graph=True, tune=True, finish_f64=finish) as b:
             b.bind(psis)
             obs, steps, conv = b.solve_imag(tol=tol, check_every=check_every, max_steps=max_steps)
         torch.cuda.synchronize()
@@ -311,21 +449,27 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--fp32", default="c64", choices=["c64", "c64_f64"],
-                    help="complex64 variant reported in the fp32 object")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="oracle seconds, split between all host threads and one")
     ap.add_argument("--latency-repeats", type=int, default=50)
-    ap.add_argument("--cache-steps", type=int, default=200,
-                    help="steps timed on the cache-resident 240x200x160 quench grid (0: skip)")
+    ap.add_argument("--quench-steps", type=int, default=1000,
+                    help="real-time steps of the 240x200x160 quench from its relaxed ground state (0: skip)")
+    ap.add_argument("--error-steps", type=int, default=500,
+                    help="steps of the large grid after which the FP32 forms are compared with complex128 "
+                         "(0: skip)")
+    ap.add_argument("--no-small-report", action="store_true",
+                    help="skip the 32^3 report (GPU and oracle observables, oracle time)")
     ap.add_argument("--only", choices=["c128", "c64", "c64_f64"], default=None,
                     help="run one dtype only (profiling runs)")
     ap.add_argument("--batch-solves", type=int, default=256,
                     help="solves in the batched imaginary-time comparison (0 skips it)")
     ap.add_argument("--batch-sample", type=int, default=32,
                     help="solves re-run in complex128 to the batch's step counts for the error figures")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="seconds of Poisson arrivals (50/s) in the serving leg (0 skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="seconds of Poisson arrivals (50/s) in each serving leg (0 skips them)")
+    ap.add_argument("--serve-dtypes", default="c64,c128",
+                    help="server variants of the serving legs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-MiB buffer three times with torch (a plain copy kernel "
                          "of known size, to scale hardware byte counters)")
@@ -358,7 +502,7 @@ def main() -> int:
     log(f"[bench] generating the {w.name} initial state")
     psi_host = inputs.initial_state(w)
 
-    dtypes = [args.only] if args.only else ["c128", args.fp32]
+    dtypes = [args.only] if args.only else ["c128", "c64", "c64_f64"]
     res = {}
     for dt in dtypes:
         log(f"[bench] timing {dt}: {args.warmup} warmup + {args.steps} steps")
@@ -379,18 +523,27 @@ def main() -> int:
         "roofline": p["roofline"],
         "kernels": p["kernels"],
         "step_hbm_frac": p["step_hbm_frac"],
+        "step_floor_frac": p["step_floor_frac"],
         "norm_drift": p["norm_drift"],
     }
     for dt in dtypes:
         if dt != primary:
             q = res[dt]
-            out["fp32"] = {"storage": "complex64", "arithmetic": "f32" if dt == "c64" else "f64",
+            out["fp32" if dt == "c64" else "fp32_storage_f64_arith"] = {
+                           "storage": "complex64", "arithmetic": "f32" if dt == "c64" else "f64",
                            "value": q["value"], "ms_per_step": q["ms_per_step"],
                            "roofline": q["roofline"], "kernels": q["kernels"],
-                           "step_hbm_frac": q["step_hbm_frac"], "norm_drift": q["norm_drift"]}
-    if args.cache_steps > 0:
-        log("[bench] the cache-resident quench grid")
-        out["cache_resident"] = cache_resident(gp, torch, args.cache_steps)
+                           "step_hbm_frac": q["step_hbm_frac"], "step_floor_frac": q["step_floor_frac"],
+                           "norm_drift": q["norm_drift"]}
+    if args.error_steps > 0:
+        log(f"[bench] FP32 forms against complex128 after {args.error_steps} steps")
+        out["fp32_error"] = large_fp32_error(gp, torch, w, psi_host, args.error_steps)
+    if args.quench_steps > 0:
+        log("[bench] the quench workload")
+        out["quench"] = quench(gp, torch, args.quench_steps)
+    if not args.no_small_report:
+        log("[bench] the 32^3 report")
+        out["small"] = small_report(gp, torch)
     if args.latency_repeats > 0:
         log("[bench] latency of the small imaginary-time solve")
         out["latency"] = latency(gp, torch, args.latency_repeats)
@@ -399,9 +552,9 @@ def main() -> int:
     if args.serve_seconds > 0:
         from paper_1206_1361_amd import serve
 
-        out["serve"] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype="c64", verify=4, log=log)
-        out["serve_real_ground_states"] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype="c64", verify=4,
-                                                    real_states=True, log=log)
+        for sd in [v for v in args.serve_dtypes.split(",") if v]:
+            key = "serve" if sd == "c64" else f"serve_{sd}"
+            out[key] = serve.run(rate=50.0, seconds=args.serve_seconds, dtype=sd, verify=4, log=log)
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on the host cores (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(w, psi_host, args.cpu_seconds)

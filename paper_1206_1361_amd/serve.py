@@ -15,8 +15,11 @@ and copied in by the server at admission; its final state is copied back
 before the result is reported.  Latency = result time - submit time on the
 server's clock.  Prints one JSON line; `--verify N` re-serves N sampled
 requests alone afterwards and checks they give the same bits as in the mix.
-With `--real-states` the ground-state requests send their (real) Gaussian
-as a real array and run on real storage, half the bytes per point.
+The server detects ground-state requests whose start has no imaginary part
+(the Gaussian starts here) and runs them on real storage, half the bytes
+per point (GP_SERVER_REAL_AUTO; `--no-real-auto` turns that off).  With
+`--real-states` the ground-state requests instead send their Gaussian as a
+real array.
 """
 from __future__ import annotations
 
@@ -61,7 +64,8 @@ def pct(v, q):
 
 
 def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_every=10, tol=1e-8,
-        imag_cap=20000, real_steps=2000, verify=8, seed=4, real_states=False, graph=True, log=None) -> dict:
+        imag_cap=20000, real_steps=2000, verify=8, seed=4, real_states=False, graph=True, real_auto=True,
+        log=None) -> dict:
     log = log or (lambda m: print(m, file=sys.stderr, flush=True))
     npd = np.complex128 if gp._dtype(dtype) == gp.C128 else np.complex64
     npr = np.float64 if npd is np.complex128 else np.float32
@@ -78,7 +82,7 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
     stop = threading.Event()
 
     with gp.Server(dtype=dtype, hbm_budget=int(budget_gib * (1 << 30)), max_slots=slots,
-                   check_every=check_every, graph=graph) as srv:
+                   check_every=check_every, graph=graph, real_auto=real_auto) as srv:
         def collector():
             while not stop.is_set() or len(results) < len(sched):
                 for r in srv.poll(wait=0.2):
@@ -147,7 +151,8 @@ def run(rate=50.0, seconds=60.0, dtype="c64", budget_gib=2.0, slots=96, check_ev
     return {
         "workload": f"serve-poisson-{rate:g}/s-{seconds:g}s", "dtype": dtype,
         "storage": ("complex128" if npd is np.complex128 else "complex64") +
-                   (f"; ground states on real {np.dtype(npr).name}" if real_states else ""),
+                   (f"; ground states sent as real {np.dtype(npr).name}" if real_states else
+                    (f"; ground states with real starts on {np.dtype(npr).name} (detected)" if real_auto else "")),
         "reductions": "f64", "requests": len(sched), "completed_ok": len(ok),
         "imag_converged": f"{sum(conv)}/{len(conv)}",
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": round(float(np.mean(lat)), 2) if lat else None,
@@ -179,9 +184,11 @@ def main() -> int:
     ap.add_argument("--real-states", action="store_true",
                     help="ground-state requests carry real states and run on real storage")
     ap.add_argument("--no-graph", action="store_true", help="launch the rounds' steps without graph replay")
+    ap.add_argument("--no-real-auto", action="store_true",
+                    help="keep real-start ground states on complex storage")
     a = ap.parse_args()
     out = run(a.rate, a.seconds, a.dtype, a.budget_gib, a.slots, a.check_every, verify=a.verify, seed=a.seed,
-              real_states=a.real_states, graph=not a.no_graph)
+              real_states=a.real_states, graph=not a.no_graph, real_auto=not a.no_real_auto)
     print(json.dumps(out), flush=True)
     return 0
 
