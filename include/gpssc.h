@@ -209,7 +209,11 @@ gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
  * (same results, faster).  One step is, in
  * order: calcnu (psi <- exp(-tau (V + g|psi|^2)) psi, tau = dt or i dt),
  * calclux, calcluy, calcluz (one Crank-Nicolson solve per grid line along
- * each axis by the precomputed Thomas recursion) and, in imaginary time,
+ * each axis: the constant tridiagonal matrix of the Thomas recursion, solved
+ * through its precomputed Toeplitz factorisation -- two first-order
+ * recurrences with one coefficient, carried between chunks of a line by a
+ * parallel scan, plus a rank-one boundary term; see gp_sweep_tables -- which
+ * equals the Thomas solution up to rounding) and, in imaginary time,
  * calcnorm.  In imaginary time psi has norm 1 when the queued work ends; the
  * per-step renormalisation is carried by the next step's first pass and a
  * final scaling pass, which equals renormalising after every step up to

@@ -79,6 +79,11 @@ struct gp_batch {
     hipGraphExec_t exec = nullptr;
     bool graph_ok = false;
     int64_t steps_done = 0;
+    // the captured step runs each class on a branch of its own (fork from
+    // and join back to `own`), so the classes' launches overlap on the device
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
 
     // GP_BATCH_FINISH_F64: the same solves in FP64 storage (complex128 for
     // complex64, float64 for float32), on buffers of the batch's own
@@ -118,6 +123,9 @@ void release(gp_batch *b)
         if (p) (void)hipHostFree(p);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t st : b->branch) (void)hipStreamDestroy(st);
     if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
 }
@@ -170,31 +178,69 @@ hipError_t upload_active(gp_batch *b)
     return hipStreamSynchronize(b->own);
 }
 
-// One step of every active solve, queued on the batch's own stream.
-hipError_t enqueue_step(gp_batch *b)
+// One step of the active solves of one class, queued on `st`.
+hipError_t enqueue_class(gp_batch *b, const Class &c, hipStream_t st)
 {
     const gpssc::Prec prec = static_cast<gpssc::Prec>(b->dtype);
     const bool real = b->mode == GP_MODE_REAL;
-    hipError_t e = hipSuccess;
+    hipError_t e = gpssc::launch_nu_x_batch(prec, real, c.chunk[0], c.nact, c.nlines, b->d_psis, b->d_xargs,
+                                            c.d_active, real ? nullptr : b->d_scales, st);
+    if (e != hipSuccess) return e;
+    e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], c.nact, c.ncol_y,
+                                    c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = gpssc::launch_strided_batch(prec, real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], c.nact, c.ncol_z,
+                                    c.ntiles_z, b->d_psis, b->d_zargs, c.d_active,
+                                    real ? nullptr : b->d_partials, b->d_part_off, st);
+    if (e != hipSuccess || real) return e;
+    return gpssc::launch_norm_finalize_batch(c.nact, c.d_active, b->d_partials, b->d_part_off,
+                                             (int)(c.grid[0] * c.grid[1]), b->d_dv, b->d_scales, b->d_flags, st);
+}
+
+// One step of every active solve, queued on the batch's own stream.
+hipError_t enqueue_step(gp_batch *b)
+{
     for (const Class &c : b->cls) {
         if (!c.nact) continue;
-        e = gpssc::launch_nu_x_batch(prec, real, c.chunk[0], c.nact, c.nlines, b->d_psis, b->d_xargs,
-                                     c.d_active, real ? nullptr : b->d_scales, b->own);
+        hipError_t e = enqueue_class(b, c, b->own);
         if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], c.nact,
-                                        c.ncol_y, c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr,
-                                        nullptr, b->own);
-        if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], c.nact,
-                                        c.ncol_z, c.ntiles_z, b->d_psis, b->d_zargs, c.d_active,
-                                        real ? nullptr : b->d_partials, b->d_part_off, b->own);
-        if (e != hipSuccess) return e;
-        if (!real) {
-            e = gpssc::launch_norm_finalize_batch(c.nact, c.d_active, b->d_partials, b->d_part_off,
-                                                  (int)(c.grid[0] * c.grid[1]), b->d_dv, b->d_scales,
-                                                  b->d_flags, b->own);
-            if (e != hipSuccess) return e;
-        }
+    }
+    return hipSuccess;
+}
+
+// The same step as a fork/join over the classes: class k on branch[k],
+// started after everything before it on `own` and joined back before
+// anything after it.  The classes touch disjoint memory (each solve's psi,
+// partials, scale and flag belong to one class), so only the order within
+// a class matters, and every solve's result is unchanged.
+// The branch streams and events, one per class (created before a capture
+// begins).
+hipError_t make_branches(gp_batch *b)
+{
+    hipError_t e = hipSuccess;
+    if (!b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    while (e == hipSuccess && b->branch.size() < b->cls.size()) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (st) b->branch.push_back(st);
+        if (ev) b->ev_join.push_back(ev);
+    }
+    return e;
+}
+
+hipError_t enqueue_step_branches(gp_batch *b)
+{
+    if (!b->ev_fork || b->branch.size() < b->cls.size()) return hipErrorInvalidValue;
+    hipError_t e = hipEventRecord(b->ev_fork, b->own);
+    for (size_t k = 0; k < b->cls.size() && e == hipSuccess; ++k) {
+        const Class &c = b->cls[k];
+        if (!c.nact) continue;
+        e = hipStreamWaitEvent(b->branch[k], b->ev_fork, 0);
+        if (e == hipSuccess) e = enqueue_class(b, c, b->branch[k]);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join[k], b->branch[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_join[k], 0);
     }
     return e;
 }
@@ -206,9 +252,10 @@ hipError_t build_graph(gp_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_ok = false;
-    hipError_t e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+    hipError_t e = make_branches(b);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = enqueue_step(b);
+    hipError_t le = enqueue_step_branches(b);
     e = hipStreamEndCapture(b->own, &b->graph);
     if (le != hipSuccess) return le;
     if (e != hipSuccess) return e;

@@ -177,6 +177,10 @@ struct gp_server {
     unsigned char *d_arena = nullptr;
     unsigned char *d_stage = nullptr;   // engine thread: complex staging of GP_SERVER_REAL_AUTO requests
     size_t stage_bytes = 0;
+    // engine thread: the captured step's per-class branches
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
 
     // guarded by mu
     std::mutex mu;
@@ -231,6 +235,9 @@ void release(gp_server *S)
 {
     free_graph(S);
     if (S->d_stage) (void)hipFree(S->d_stage);
+    if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+    for (hipEvent_t e : S->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t st : S->branch) (void)hipStreamDestroy(st);
     for (SClass &c : S->cls) {
         if (c.d_list) (void)hipFree(c.d_list);
         if (c.d_due) (void)hipFree(c.d_due);
@@ -370,29 +377,63 @@ hipError_t upload_lists(gp_server *S)
     return hipSuccess;
 }
 
-hipError_t enqueue_step(gp_server *S)
+// The branch streams and events of the captured step, one per class
+// (created before a capture begins).
+hipError_t make_branches(gp_server *S)
+{
+    hipError_t e = hipSuccess;
+    if (!S->ev_fork) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
+    while (e == hipSuccess && S->branch.size() < S->cls.size()) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (st) S->branch.push_back(st);
+        if (ev) S->ev_join.push_back(ev);
+    }
+    return e;
+}
+
+// One step of the resident solves of one class, queued on `st`.
+hipError_t enqueue_class(gp_server *S, const SClass &c, hipStream_t st)
 {
     double *base = reinterpret_cast<double *>(S->d_arena);
+    const int n = (int)c.slots.size();
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(c.dt);
+    hipError_t e = gpssc::launch_nu_x_batch(prec, c.real, c.chunk[0], n, c.nlines, S->d_psis, S->d_xargs, c.d_list,
+                                            c.real ? nullptr : S->d_scales, st);
+    if (e != hipSuccess) return e;
+    e = gpssc::launch_strided_batch(prec, c.real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], n, c.ncol_y, c.ntiles_y,
+                                    S->d_psis, S->d_yargs, c.d_list, nullptr, nullptr, st);
+    if (e != hipSuccess) return e;
+    e = gpssc::launch_strided_batch(prec, c.real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], n, c.ncol_z, c.ntiles_z,
+                                    S->d_psis, S->d_zargs, c.d_list, c.real ? nullptr : base, S->d_part_off, st);
+    if (e != hipSuccess || c.real) return e;
+    return gpssc::launch_norm_finalize_batch(n, c.d_list, base, S->d_part_off, (int)(c.grid[0] * c.grid[1]), S->d_dv,
+                                             S->d_scales, S->d_flags, st);
+}
+
+// One step of every resident solve.  Inside a capture the classes become
+// parallel branches (fork from and join back to the server's stream): they
+// touch disjoint memory, so only the order within a class matters.
+hipError_t enqueue_step(gp_server *S, bool branches = false)
+{
     hipError_t e = hipSuccess;
-    for (const SClass &c : S->cls) {
-        const int n = (int)c.slots.size();
-        if (!n) continue;
-        const gpssc::Prec prec = static_cast<gpssc::Prec>(c.dt);
-        e = gpssc::launch_nu_x_batch(prec, c.real, c.chunk[0], n, c.nlines, S->d_psis, S->d_xargs, c.d_list,
-                                     c.real ? nullptr : S->d_scales, S->stream);
-        if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], n, c.ncol_y,
-                                        c.ntiles_y, S->d_psis, S->d_yargs, c.d_list, nullptr, nullptr, S->stream);
-        if (e != hipSuccess) return e;
-        e = gpssc::launch_strided_batch(prec, c.real, c.chunk[2], c.xt_z, c.cols_z, c.lanes[2], n, c.ncol_z,
-                                        c.ntiles_z, S->d_psis, S->d_zargs, c.d_list, c.real ? nullptr : base,
-                                        S->d_part_off, S->stream);
-        if (e != hipSuccess) return e;
-        if (!c.real) {
-            e = gpssc::launch_norm_finalize_batch(n, c.d_list, base, S->d_part_off, (int)(c.grid[0] * c.grid[1]),
-                                                  S->d_dv, S->d_scales, S->d_flags, S->stream);
-            if (e != hipSuccess) return e;
+    if (branches) {
+        if (!S->ev_fork || S->branch.size() < S->cls.size()) return hipErrorInvalidValue;   // see make_branches
+        e = hipEventRecord(S->ev_fork, S->stream);
+    }
+    for (size_t k = 0; k < S->cls.size() && e == hipSuccess; ++k) {
+        const SClass &c = S->cls[k];
+        if (c.slots.empty()) continue;
+        if (!branches) {
+            e = enqueue_class(S, c, S->stream);
+            continue;
         }
+        e = hipStreamWaitEvent(S->branch[k], S->ev_fork, 0);
+        if (e == hipSuccess) e = enqueue_class(S, c, S->branch[k]);
+        if (e == hipSuccess) e = hipEventRecord(S->ev_join[k], S->branch[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(S->stream, S->ev_join[k], 0);
     }
     return e;
 }
@@ -400,9 +441,10 @@ hipError_t enqueue_step(gp_server *S)
 hipError_t capture(gp_server *S)
 {
     free_graph(S);
-    hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = make_branches(S);
+    if (e == hipSuccess) e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = enqueue_step(S);
+    hipError_t le = enqueue_step(S, true);
     e = hipStreamEndCapture(S->stream, &S->graph);
     if (le != hipSuccess) return le;
     if (e != hipSuccess) return e;
