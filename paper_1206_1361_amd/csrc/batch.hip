@@ -41,6 +41,7 @@ struct Class : ClassShape {
     std::vector<int> members;
     int nact = 0;
     int *d_active = nullptr;     // active solve indices
+    int x_lines = 0;             // x lines per wavefront (0: the library's rule; GP_BATCH_TUNE times them)
 };
 
 }  // namespace
@@ -184,7 +185,7 @@ hipError_t enqueue_class(gp_batch *b, const Class &c, hipStream_t st)
     const gpssc::Prec prec = static_cast<gpssc::Prec>(b->dtype);
     const bool real = b->mode == GP_MODE_REAL;
     hipError_t e = gpssc::launch_nu_x_batch(prec, real, c.chunk[0], c.nact, c.nlines, b->d_psis, b->d_xargs,
-                                            c.d_active, real ? nullptr : b->d_scales, st);
+                                            c.d_active, real ? nullptr : b->d_scales, st, c.x_lines);
     if (e != hipSuccess) return e;
     e = gpssc::launch_strided_batch(prec, real, c.chunk[1], c.xt_y, c.cols_y, c.lanes[1], c.nact, c.ncol_y,
                                     c.ntiles_y, b->d_psis, b->d_yargs, c.d_active, nullptr, nullptr, st);
@@ -337,6 +338,33 @@ hipError_t tune_class(gp_batch *b, Class &c)
             c.cols_z = best_cols;
         }
     }
+    // x: lines per wavefront, with every member of the class in the launch
+    // (all aliased to the scratch: only the launch shape is timed)
+    int *d_all = nullptr;
+    const int nm = (int)c.members.size();
+    if (e == hipSuccess) e = hipMalloc(&d_all, sizeof(int) * (size_t)nm);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_all, c.members.data(), sizeof(int) * (size_t)nm, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    float best_x = 1e30f;
+    for (int L = 1; L <= gpssc::x_max_lines_per_wave(c.chunk[0]) && e == hipSuccess; L *= 2) {
+        auto run = [&] {
+            return gpssc::launch_nu_x_batch(prec, real, c.chunk[0], nm, c.nlines, d_ptr, b->d_xargs, d_all, nullptr,
+                                            b->own, L);
+        };
+        e = run();  // warm
+        if (e == hipSuccess) e = hipEventRecord(t0, b->own);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+        if (e == hipSuccess) e = hipEventRecord(t1, b->own);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e == hipSuccess && ms < best_x) {
+            best_x = ms;
+            c.x_lines = L;
+        }
+    }
+    if (d_all) (void)hipFree(d_all);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     if (d_m0) (void)hipFree(d_m0);
@@ -751,11 +779,12 @@ gp_status gp_batch_describe(const gp_batch *b, char *buf, size_t len)
     if (!b || !buf || len == 0) return fail(GP_ERR_INVALID, "bad gp_batch_describe arguments");
     std::string d = std::to_string(b->n) + " solves, " + std::to_string(b->cls.size()) + " classes";
     for (const Class &c : b->cls) {
-        char t[200];
+        char t[256];
         std::snprintf(t, sizeof t,
-                      " | %lldx%lldx%lld: %zu solves, x chunk %d, y chunk %d x %d (%d cols%s), z chunk %d x %d "
-                      "(%d cols%s)",
+                      " | %lldx%lldx%lld: %zu solves, x chunk %d (%s lines per wave), y chunk %d x %d (%d cols%s), "
+                      "z chunk %d x %d (%d cols%s)",
                       (long long)c.grid[0], (long long)c.grid[1], (long long)c.grid[2], c.members.size(), c.chunk[0],
+                      c.x_lines ? std::to_string(c.x_lines).c_str() : "auto",
                       c.chunk[1], c.lanes[1], c.xt_y * c.cols_y, c.cols_y == 2 ? " in pairs" : "", c.chunk[2],
                       c.lanes[2], c.xt_z * c.cols_z, c.cols_z == 2 ? " in pairs" : "");
         d += t;

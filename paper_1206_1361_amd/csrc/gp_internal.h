@@ -422,11 +422,13 @@ hipError_t launch_observables(Prec prec, const void *psi, const ObsArgs<double> 
 
 // ---- batched launchers: one launch covers every active solve of one grid
 // shape.  psis[i], args[i]: solve i's psi and arguments (device arrays);
-// active[0..nact): the solves to advance. ----
+// active[0..nact): the solves to advance.  lines (x): lines per wavefront,
+// 1, 2 or 4 up to x_max_lines_per_wave(chunk), or 0 for x_lines_per_wave's
+// rule; it does not enter the rounding. ----
 
 hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlines, void *const *psis,
                              const void *args, const int *active, const double *scales,
-                             hipStream_t stream);
+                             hipStream_t stream, int lines = 0);
 
 // partials + part_off[i]: solve i's per-line norm partials (NULL: none).
 // cols: columns per thread as in launch_strided (2: every active solve's psi

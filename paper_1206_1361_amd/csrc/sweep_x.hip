@@ -373,12 +373,13 @@ static void launch_batch_l(int L, dim3 grid, hipStream_t stream, S *const *p, co
 }
 
 template <typename S, typename A, bool REAL>
-static hipError_t launch_batch_c(int chunk, int nact, int nlines, void *const *psis, const void *args,
+static hipError_t launch_batch_c(int chunk, int lines, int nact, int nlines, void *const *psis, const void *args,
                                  const int *active, const double *scales, hipStream_t stream)
 {
     const int64_t total = (int64_t)nact * nlines;
     if (total > INT32_MAX) return hipErrorInvalidValue;
-    const int L = x_lines_per_wave(chunk, total);
+    if (lines < 0 || lines > x_max_lines_per_wave(chunk) || (lines & (lines - 1))) return hipErrorInvalidValue;
+    const int L = lines ? lines : x_lines_per_wave(chunk, total);
     const dim3 grid((unsigned)((total + L - 1) / L));
     S *const *p = reinterpret_cast<S *const *>(psis);
     const XBatchArgs<A> *a = static_cast<const XBatchArgs<A> *>(args);
@@ -399,20 +400,22 @@ static hipError_t launch_batch_c(int chunk, int nact, int nlines, void *const *p
 
 hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlines, void *const *psis,
                              const void *args, const int *active, const double *scales,
-                             hipStream_t stream)
+                             hipStream_t stream, int lines)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
     if (nact <= 0) return hipSuccess;
-#define GP_XB_PREC(S, A)                                                                      \
-    return real ? launch_batch_c<S, A, true>(chunk, nact, nlines, psis, args, active, scales, stream) \
-                : launch_batch_c<S, A, false>(chunk, nact, nlines, psis, args, active, scales, stream);
+#define GP_XB_PREC(S, A)                                                                                   \
+    return real ? launch_batch_c<S, A, true>(chunk, lines, nact, nlines, psis, args, active, scales, stream) \
+                : launch_batch_c<S, A, false>(chunk, lines, nact, nlines, psis, args, active, scales, stream);
     switch (prec) {
     case PREC_C64: GP_XB_PREC(float2, float)
     case PREC_C64_F64: GP_XB_PREC(float2, double)
     case PREC_C128: GP_XB_PREC(double2, double)
     // real storage: imaginary time only (real time was refused above)
-    case PREC_R64: return launch_batch_c<double, double, false>(chunk, nact, nlines, psis, args, active, scales, stream);
-    case PREC_R32: return launch_batch_c<float, float, false>(chunk, nact, nlines, psis, args, active, scales, stream);
+    case PREC_R64:
+        return launch_batch_c<double, double, false>(chunk, lines, nact, nlines, psis, args, active, scales, stream);
+    case PREC_R32:
+        return launch_batch_c<float, float, false>(chunk, lines, nact, nlines, psis, args, active, scales, stream);
     }
 #undef GP_XB_PREC
     return hipErrorInvalidValue;
