@@ -49,6 +49,19 @@ def _compile(src: pathlib.Path) -> pathlib.Path:
     return obj
 
 
+PROBE_SRC = PKG / "probe" / "pattern_copy.hip"
+PROBE_BIN = PKG / "probe" / "pattern_copy"
+
+
+def build_probe() -> pathlib.Path:
+    """The access-pattern probe (a measurement tool, not part of the library)."""
+    cmd = [HIPCC, *[f for f in COMMON if f != "-fPIC"], "-o", str(PROBE_BIN), str(PROBE_SRC)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"building the probe failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return PROBE_BIN
+
+
 def build(verbose: bool = False) -> pathlib.Path:
     BUILD.mkdir(exist_ok=True)
     srcs = sources()
@@ -60,8 +73,9 @@ def build(verbose: bool = False) -> pathlib.Path:
     if res.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIBRARY)
+    build_probe()
     if verbose:
-        print(f"built {LIBRARY}", file=sys.stderr)
+        print(f"built {LIBRARY} and {PROBE_BIN}", file=sys.stderr)
     return LIBRARY
 
 
