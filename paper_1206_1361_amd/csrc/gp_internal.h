@@ -358,20 +358,18 @@ constexpr int x_lines_per_wave(int chunk, int64_t nlines)
 // calcnu + calclux.  zt: boundary correction by position (complex, the
 // arithmetic type).  scale: NULL or device double (pending 1/sqrt(N)).
 // partials: NULL or one double per x line (sum |psi|^2 of its output).
-// nblocks: one-wavefront blocks to launch (each takes x_lines_per_wave(chunk,
-// ny nz) lines at a time and loops; 0 or enough for every line = one pass).
-hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
+// One one-wavefront block per x_lines_per_wave(chunk, ny nz) lines.
+hipError_t launch_nu_x(Prec prec, bool real, int chunk, void *psi, const void *args,
                        const void *zt, const double *scale, double *partials, hipStream_t stream);
 
 // calcluy / calcluz over ceil(nx/(xt cols)) x nouter tiles.  cols: columns
 // per thread, 1, or 2 for complex64 with FP32 arithmetic (then nx and both
-// strides must be even and psi 16-byte aligned).  nblocks: blocks to launch
-// (each loops over tiles; 0 or >= the tile count = one per tile).  zt:
+// strides must be even and psi 16-byte aligned); one block per tile.  zt:
 // boundary correction by position.  partials: NULL, or nx * nouter doubles:
 // sum |psi|^2 of each line's output, at outer * nx + column.
 // xcd_ranges: hand each XCD a contiguous range of tiles (the y sweep; see
 // calclu_strided_kernel).
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter, int nblocks,
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter,
                           void *psi, const void *args, const void *zt, double *partials, bool xcd_ranges,
                           hipStream_t stream);
 

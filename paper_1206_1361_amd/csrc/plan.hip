@@ -430,7 +430,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
                 return gpssc::launch_nu_r(prec, real, p->ax[0].chunk, (int)(p->n[1] * p->n[2]), psi, rargs, scale,
                                           nd == 1 ? parts : nullptr, p->stream);
             }
-            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, p->x_blocks, psi, xargs,
+            return gpssc::launch_nu_x(prec, real, p->ax[0].chunk, psi, xargs,
                                       T + p->tab_off[0], scale, nd == 1 ? parts : nullptr, p->stream);
         });
         if (e != hipSuccess) break;
@@ -440,9 +440,8 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
                     return gpssc::launch_stream(prec, real, p->blk_y, spair ? 2 : 1, (int)p->n[2], psi, yargs,
                                                 T + p->tab_off[1], nd == 2 ? parts : nullptr, p->stream);
                 return gpssc::launch_strided(prec, real, p->ax[1].chunk, pair_y ? p->xt2_y : p->xt_y,
-                                             pair_y ? 2 : 1, (int)p->n[2], pair_y ? p->y2_blocks : p->y_blocks,
-                                             psi, yargs, T + p->tab_off[1], nd == 2 ? parts : nullptr,
-                                             true, p->stream);
+                                             pair_y ? 2 : 1, (int)p->n[2], psi, yargs, T + p->tab_off[1],
+                                             nd == 2 ? parts : nullptr, true, p->stream);
             });
             if (e != hipSuccess) break;
         }
@@ -452,8 +451,8 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
                     return gpssc::launch_stream(prec, real, p->blk_z, spair ? 2 : 1, (int)p->n[1], psi, zargs,
                                                 T + p->tab_off[2], parts, p->stream);
                 return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
-                                             pair_z ? 2 : 1, (int)p->n[1], pair_z ? p->z2_blocks : p->z_blocks,
-                                             psi, zargs, T + p->tab_off[2], parts, false, p->stream);
+                                             pair_z ? 2 : 1, (int)p->n[1], psi, zargs, T + p->tab_off[2], parts,
+                                             false, p->stream);
             });
         }
         if (e != hipSuccess || real) continue;

@@ -223,7 +223,7 @@ __device__ __forceinline__ void sincos_reduced(A x, A *s, A *c)
     const A r = fma(-k, H::p3, fma(-k, H::p2, fma(-k, H::p1, x)));
     A sr, cr;
     sincos_taylor(r, &sr, &cr);
-    const int q = (int)((long long)k & 3);
+    const int q = (int)k & 3;   // |k| < 2^31 for every phase the reduction serves
     A ss = (q & 1) ? cr : sr;
     A cc = (q & 1) ? sr : cr;
     if (q & 2) ss = -ss;

@@ -241,8 +241,11 @@ __device__ __forceinline__ void store_x_row(S *__restrict__ row, const S (&v)[C]
     }
 }
 
-// One wavefront per block; block b solves lines b, b + G, ... (G =
-// gridDim.x).
+// One wavefront per block; block b solves line b (the grid has one block
+// per line).  A block takes one line and no more: a loop over lines would
+// keep every argument live across its iterations, more uniform values than
+// the scalar registers hold, and the spills into vector lanes would cost
+// about a fifth of the kernel's vector instructions.
 // partials: NULL, or one double per line receiving sum |psi|^2 of the stored
 // line (the norm partials of imaginary time when x is the only variable),
 // summed per lane in row order, then over the lanes by a fixed tree.
@@ -255,7 +258,9 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
     const int lane = threadIdx.x;
     const int nlines = a.ny * a.nz;
     const A s = scale ? (A)(*scale) : (A)1;
-    for (int line = blockIdx.x; line < nlines; line += gridDim.x) {
+    const int line = blockIdx.x;
+    if (line >= nlines) return;
+    {
         S *row = psi + (int64_t)line * a.nx;
         S v[C];
         load_x_row(v, row, a.nx);
@@ -278,13 +283,13 @@ calcnu_lux_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__restrict
             for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_down(acc, d, kWave);
             if (lane == 0) partials[line] = acc;
         }
-        __syncthreads();  // buf is free for the next line
     }
 }
 
 // Short lines (chunk <= 4): one wavefront per block; block b solves lines
-// bL .. bL + L - 1 together, then the lines G L further on (G = gridDim.x).
-// Past the last line a slot solves the last line again and stores nothing.
+// bL .. bL + L - 1 together (one block per L lines, for the reason given
+// above).  Past the last line a slot solves the last line again and stores
+// nothing.
 // partials as in calcnu_lux_kernel.
 template <typename S, typename A, int C, int L, bool REAL>
 __global__ void __launch_bounds__(kWave)
@@ -296,7 +301,9 @@ calcnu_lux_lines_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__re
     const int nx = a.nx;
     const int nlines = a.ny * a.nz;
     const A s = scale ? (A)(*scale) : (A)1;
-    for (int base = blockIdx.x * L; base < nlines; base += gridDim.x * L) {
+    const int base = blockIdx.x * L;
+    if (base >= nlines) return;
+    {
         auto ln = [&](int l) { return XLine<A>{zt, s, min(base + l, nlines - 1)}; };
         S v[L][C];
 #pragma unroll
@@ -320,7 +327,6 @@ calcnu_lux_lines_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__re
                 if (lane == 0) partials[ln(l).line] = acc;
             }
         }
-        __syncthreads();  // buf is free for the next lines
     }
 }
 
@@ -444,14 +450,13 @@ static void launch_plain_l(int L, dim3 grid, hipStream_t stream, S *p, const XAr
 }
 
 template <typename S, typename A, bool REAL>
-static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, const void *zt,
+static hipError_t launch_c(int chunk, void *psi, const void *args, const void *zt,
                            const double *scale, double *partials, hipStream_t stream)
 {
     const XArgs<A> &a = *static_cast<const XArgs<A> *>(args);
     const int nlines = a.ny * a.nz;
     const int L = x_lines_per_wave(chunk, nlines);
-    const int need = (nlines + L - 1) / L;
-    const dim3 grid((unsigned)(nblocks > 0 && nblocks < need ? nblocks : need));
+    const dim3 grid((unsigned)((nlines + L - 1) / L));
     S *p = static_cast<S *>(psi);
     const cx<A> *z = static_cast<const cx<A> *>(zt);
 #define GP_X_CASE(CC)                                                                   \
@@ -471,20 +476,20 @@ static hipError_t launch_c(int chunk, int nblocks, void *psi, const void *args, 
     return hipGetLastError();
 }
 
-hipError_t launch_nu_x(Prec prec, bool real, int chunk, int nblocks, void *psi, const void *args,
+hipError_t launch_nu_x(Prec prec, bool real, int chunk, void *psi, const void *args,
                        const void *zt, const double *scale, double *partials, hipStream_t stream)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
 #define GP_X_PREC(S, A)                                                                   \
-    return real ? launch_c<S, A, true>(chunk, nblocks, psi, args, zt, scale, partials, stream)  \
-                : launch_c<S, A, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
+    return real ? launch_c<S, A, true>(chunk, psi, args, zt, scale, partials, stream)  \
+                : launch_c<S, A, false>(chunk, psi, args, zt, scale, partials, stream);
     switch (prec) {
     case PREC_C64: GP_X_PREC(float2, float)
     case PREC_C64_F64: GP_X_PREC(float2, double)
     case PREC_C128: GP_X_PREC(double2, double)
     // real storage: imaginary time only (real time was refused above)
-    case PREC_R64: return launch_c<double, double, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
-    case PREC_R32: return launch_c<float, float, false>(chunk, nblocks, psi, args, zt, scale, partials, stream);
+    case PREC_R64: return launch_c<double, double, false>(chunk, psi, args, zt, scale, partials, stream);
+    case PREC_R32: return launch_c<float, float, false>(chunk, psi, args, zt, scale, partials, stream);
     }
 #undef GP_X_PREC
     return hipErrorInvalidValue;

@@ -179,13 +179,15 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     }
 }
 
-// Tiles are numbered column-tile fastest; block b solves tiles t, t + G, ...
-// (G = gridDim.x); the plan launches one block per tile.  t = b, or with
-// xcd_ranges (and G a multiple of 8) t = (b mod 8) G/8 + b/8: blocks are
-// handed to the 8 XCDs in turn, so this gives each XCD a contiguous range of
-// tiles, and the blocks running on one XCD read neighbouring column tiles
-// (whole rows) rather than every eighth one.  LDS is reused from one tile to
-// the next.
+// Tiles are numbered column-tile fastest; the grid has one block per tile
+// (G = gridDim.x blocks) and block b solves tile t = b, or with xcd_ranges
+// (and G a multiple of 8) t = (b mod 8) G/8 + b/8: blocks are handed to the
+// 8 XCDs in turn, so this gives each XCD a contiguous range of tiles, and the
+// blocks running on one XCD read neighbouring column tiles (whole rows)
+// rather than every eighth one.  A block takes one tile and no more: a loop
+// over tiles would keep every argument live across its iterations, more
+// uniform values than the scalar registers hold, and the spills into vector
+// lanes would cost about an eighth of the kernel's vector instructions.
 template <typename S, typename A, int C, bool REAL, bool NORM, int W>
 __global__ void __launch_bounds__(kMaxBlockYZ)
 calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__restrict__ zt,
@@ -193,13 +195,11 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
 {
     extern __shared__ unsigned char smem_raw[];
     const int b = blockIdx.x, G = gridDim.x;
-    const int t0 = xcd_ranges && G % 8 == 0 ? (b % 8) * (G / 8) + b / 8 : b;
-    for (int tile = t0; tile < ntiles; tile += G) {
-        const int outer = tile / ncol_tiles;
-        const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
-        solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, tile, col0, outer);
-        __syncthreads();  // LDS is free for the next tile
-    }
+    const int tile = xcd_ranges && G % 8 == 0 ? (b % 8) * (G / 8) + b / 8 : b;
+    if (tile >= ntiles) return;
+    const int outer = tile / ncol_tiles;
+    const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
+    solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, tile, col0, outer);
 }
 
 // Batched: block b solves tile b % ntiles of solve active[b / ntiles].
@@ -296,7 +296,7 @@ hipError_t launch_strided_batch(Prec prec, bool real, int chunk, int xt, int col
 }
 
 template <typename S, typename A, bool REAL, int W>
-static hipError_t launch_tw(int chunk, int xt, int nouter, int nblocks, void *psi, const void *args,
+static hipError_t launch_tw(int chunk, int xt, int nouter, void *psi, const void *args,
                             const void *zt, double *partials, int xcd, hipStream_t stream)
 {
     const SArgs<A> &a = *static_cast<const SArgs<A> *>(args);
@@ -307,7 +307,7 @@ static hipError_t launch_tw(int chunk, int xt, int nouter, int nblocks, void *ps
         return hipErrorInvalidValue;
     const int ncol = (a.nx + xt * W - 1) / (xt * W);
     const int ntiles = ncol * nouter;
-    const dim3 grid((unsigned)(nblocks > 0 && nblocks < ntiles ? nblocks : ntiles));
+    const dim3 grid((unsigned)ntiles);
     const dim3 block((unsigned)xt, (unsigned)P);
     const size_t lds = 2 * (size_t)xt * P * sizeof(col_t<S, A, W>);
     S *p = static_cast<S *>(psi);
@@ -331,37 +331,37 @@ static hipError_t launch_tw(int chunk, int xt, int nouter, int nblocks, void *ps
 }
 
 template <typename S, typename A, bool REAL>
-static hipError_t launch_t(int chunk, int xt, int cols, int nouter, int nblocks, void *psi, const void *args,
+static hipError_t launch_t(int chunk, int xt, int cols, int nouter, void *psi, const void *args,
                            const void *zt, double *partials, int xcd, hipStream_t stream)
 {
     if (cols == 2) {
         if constexpr (std::is_same<S, float2>::value && std::is_same<A, float>::value)
-            return launch_tw<S, A, REAL, 2>(chunk, xt, nouter, nblocks, psi, args, zt, partials, xcd, stream);
+            return launch_tw<S, A, REAL, 2>(chunk, xt, nouter, psi, args, zt, partials, xcd, stream);
         return hipErrorInvalidValue;
     }
     if (cols != 1) return hipErrorInvalidValue;
-    return launch_tw<S, A, REAL, 1>(chunk, xt, nouter, nblocks, psi, args, zt, partials, xcd, stream);
+    return launch_tw<S, A, REAL, 1>(chunk, xt, nouter, psi, args, zt, partials, xcd, stream);
 }
 
-hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter, int nblocks,
+hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int nouter,
                           void *psi, const void *args, const void *zt, double *partials, bool xcd_ranges,
                           hipStream_t stream)
 {
     if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
     const int xcd = xcd_ranges ? 1 : 0;
 #define GP_S_PREC(S, A)                                                                                      \
-    return real ? launch_t<S, A, true>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, xcd, stream) \
-                : launch_t<S, A, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, xcd, stream);
+    return real ? launch_t<S, A, true>(chunk, xt, cols, nouter, psi, args, zt, partials, xcd, stream) \
+                : launch_t<S, A, false>(chunk, xt, cols, nouter, psi, args, zt, partials, xcd, stream);
     switch (prec) {
     case PREC_C64: GP_S_PREC(float2, float)
     case PREC_C64_F64: GP_S_PREC(float2, double)
     case PREC_C128: GP_S_PREC(double2, double)
     // real storage: imaginary time only (real time was refused above)
     case PREC_R64:
-        return launch_t<double, double, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, xcd,
+        return launch_t<double, double, false>(chunk, xt, cols, nouter, psi, args, zt, partials, xcd,
                                                stream);
     case PREC_R32:
-        return launch_t<float, float, false>(chunk, xt, cols, nouter, nblocks, psi, args, zt, partials, xcd,
+        return launch_t<float, float, false>(chunk, xt, cols, nouter, psi, args, zt, partials, xcd,
                                              stream);
     }
 #undef GP_S_PREC
