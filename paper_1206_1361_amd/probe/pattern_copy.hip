@@ -54,18 +54,20 @@ __global__ void __launch_bounds__(1024) tile_pass(d2 *psi, int nx, int n, long s
         if (pos0 + c < n) __builtin_nontemporal_store(u[c] * scale, base + (long)c * stride);
 }
 
-// Block b covers elements [b 256 E, (b + 1) 256 E); thread t takes
-// t, t + 256, ... within it.
+// Block b (T threads) covers elements [b T E, (b + 1) T E); thread t takes
+// t, t + T, ... within it.  Dynamic LDS, when asked for, only limits how
+// many blocks share a CU.
 template <int E>
 __global__ void __launch_bounds__(256) stream_pass(d2 *psi, long n, double scale)
 {
-    const long base = (long)blockIdx.x * 256 * E + threadIdx.x;
+    const long T = blockDim.x;
+    const long base = (long)blockIdx.x * T * E + threadIdx.x;
     d2 u[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = base + 256L * e < n ? __builtin_nontemporal_load(psi + base + 256L * e) : d2{0, 0};
+    for (int e = 0; e < E; ++e) u[e] = base + T * e < n ? __builtin_nontemporal_load(psi + base + T * e) : d2{0, 0};
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        if (base + 256L * e < n) __builtin_nontemporal_store(u[e] * scale, psi + base + 256L * e);
+        if (base + T * e < n) __builtin_nontemporal_store(u[e] * scale, psi + base + T * e);
 }
 
 int main(int argc, char **argv)
@@ -105,6 +107,31 @@ int main(int argc, char **argv)
     report("stream, 16 elements per thread", time_it([&] {
                hipLaunchKernelGGL(stream_pass<16>, dim3((unsigned)((N + 4095) / 4096)), dim3(256), 0, nullptr, psi, N, scale);
            }));
+    // one-wavefront blocks taking one 512-element row each, as the x sweep
+    // moves a complex128 line, with at most W blocks per CU (LDS-limited)
+    for (int w : {0, 32, 16, 8, 4}) {
+        const size_t lds = w ? (160 * 1024) / w - 64 : 0;
+        char name[96];
+        std::snprintf(name, sizeof name, "stream, 64-thread blocks x 8 elements%s%d", w ? ", <= waves/CU " : "", w);
+        if (!w) std::snprintf(name, sizeof name, "stream, 64-thread blocks x 8 elements");
+        report(name, time_it([&] {
+                   hipLaunchKernelGGL(stream_pass<8>, dim3((unsigned)((N + 511) / 512)), dim3(64), lds, nullptr, psi, N, scale);
+               }));
+    }
+    report("stream, 64-thread blocks x 1 element", time_it([&] {
+               hipLaunchKernelGGL(stream_pass<1>, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, nullptr, psi, N, scale);
+           }));
+    report("stream, 256-thread blocks x 2 elements", time_it([&] {
+               hipLaunchKernelGGL(stream_pass<2>, dim3((unsigned)((N + 511) / 512)), dim3(256), 0, nullptr, psi, N, scale);
+           }));
+    for (int w : {16, 12}) {
+        const size_t lds = (160 * 1024) / (w / 4) - 64;   // at most 64 KiB per block
+        char name[96];
+        std::snprintf(name, sizeof name, "stream, 256-thread blocks x 1 element, <= waves/CU %d", w);
+        report(name, time_it([&] {
+                   hipLaunchKernelGGL(stream_pass<1>, dim3((unsigned)((N + 255) / 256)), dim3(256), lds, nullptr, psi, N, scale);
+               }));
+    }
     struct Shape {
         int axis, xt, c, xcd, pad;
     };
