@@ -318,8 +318,12 @@ typedef struct gp_batch gp_batch;
 enum {
     GP_BATCH_GRAPH = 1,  /* capture one step of all classes in a HIP graph and replay it */
     GP_BATCH_TUNE = 2,   /* time the y/z block widths per class at creation (scratch memory) */
-    GP_BATCH_FINISH_F64 = 4  /* imaginary-time GP_C64 / GP_R32 batches: gp_batch_solve_imag finishes
+    GP_BATCH_FINISH_F64 = 4, /* imaginary-time GP_C64 / GP_R32 batches: gp_batch_solve_imag finishes
                                 each solve in FP64 storage (see there) */
+    GP_BATCH_ONE_LAUNCH = 8  /* each sweep of a step one launch over every class (blocks find their
+                                class and solve with its chunking and tile shape) instead of one launch
+                                per class.  Currently refused with GP_ERR_UNSUPPORTED: its first GPU test
+                                ended in a device fault whose cause is not yet found */
 };
 
 /* Creates a batch of nsolves solves.  Per solve i: grids[3i..3i+2] (Nx, Ny,

@@ -45,6 +45,7 @@ EXPORTS = (
 BATCH_GRAPH = 1
 BATCH_TUNE = 2
 BATCH_FINISH_F64 = 4
+BATCH_ONE_LAUNCH = 8
 SERVER_GRAPH = 1
 SERVER_REAL_AUTO = 2
 
@@ -479,7 +480,8 @@ class Batch:
     3-tuple), dt, trap (gamma, nu, lambda), g.  All share mode and dtype.
     """
 
-    def __init__(self, specs, mode="imag", dtype="c128", graph=True, tune=False, stream=None, finish_f64=False):
+    def __init__(self, specs, mode="imag", dtype="c128", graph=True, tune=False, stream=None, finish_f64=False,
+                 one_launch=False):
         import numpy as np
         import torch
 
@@ -498,7 +500,8 @@ class Batch:
         self.mode = _mode(mode)
         self.dtype = _dtype(dtype)
         self.torch_dtype = torch_dtype_of(self.dtype)
-        flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0) | (BATCH_FINISH_F64 if finish_f64 else 0)
+        flags = ((BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0) | (BATCH_FINISH_F64 if finish_f64 else 0)
+                 | (BATCH_ONE_LAUNCH if one_launch else 0))
         self._handle = ctypes.c_void_p()
         self._psis = None
         dp = ctypes.POINTER(ctypes.c_double)

@@ -91,6 +91,23 @@ struct gp_batch {
     gp_batch *fin = nullptr;
     unsigned char *d_shadow = nullptr;
     std::vector<void *> shadow;
+
+    // GP_BATCH_ONE_LAUNCH: each sweep of a step is one launch over every
+    // class with active solves, described by these arrays (device, with a
+    // pinned staging copy); rebuilt whenever the active lists or the class
+    // shapes change
+    gpssc::XClassDesc *d_xcls = nullptr;
+    gpssc::YZClassDesc *d_ycls = nullptr, *d_zcls = nullptr;
+    gpssc::NormClassDesc *d_ncls = nullptr;
+    unsigned char *h_cls = nullptr;
+    struct {
+        int ncls = 0;
+        int xblocks = 0, yblocks = 0, zblocks = 0, nblocks = 0;
+        int cmax_x = 1, cmax_y = 1, cmax_z = 1;
+        int lds_x = 0;
+        int thr_y = 0, thr_z = 0;
+        size_t lds_y = 0, lds_z = 0;
+    } one;
 };
 
 namespace {
@@ -110,6 +127,10 @@ void release(gp_batch *b)
         release(b->fin);
     }
     if (b->d_shadow) (void)hipFree(b->d_shadow);
+    void *cls_dev[] = {b->d_xcls, b->d_ycls, b->d_zcls, b->d_ncls};
+    for (void *p : cls_dev)
+        if (p) (void)hipFree(p);
+    if (b->h_cls) (void)hipHostFree(b->h_cls);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (Class &c : b->cls)
@@ -156,6 +177,66 @@ std::vector<unsigned char> pack_batch_args(const gp_batch *b, int which)
     return out;
 }
 
+// Bytes of one value a y/z thread holds per row (LDS per thread = 2 of
+// them): the arithmetic's complex (or real) value, or a complex64 pair.
+size_t yz_value_bytes(gp_dtype dtype, int cols)
+{
+    if (cols == 2) return 16;
+    if (dtype == GP_R32) return 4;
+    if (dtype == GP_R64 || dtype == GP_C64) return 8;
+    return 16;
+}
+
+// The class descriptors of GP_BATCH_ONE_LAUNCH from the classes' active
+// counts and shapes (classes without active solves are left out), uploaded
+// on the batch's own queue.
+hipError_t upload_classes(gp_batch *b)
+{
+    if (!(b->flags & GP_BATCH_ONE_LAUNCH)) return hipSuccess;
+    const size_t nc = b->cls.size();
+    gpssc::XClassDesc *hx = reinterpret_cast<gpssc::XClassDesc *>(b->h_cls);
+    gpssc::YZClassDesc *hy = reinterpret_cast<gpssc::YZClassDesc *>(hx + nc);
+    gpssc::YZClassDesc *hz = hy + nc;
+    gpssc::NormClassDesc *hn = reinterpret_cast<gpssc::NormClassDesc *>(hz + nc);
+    auto &o = b->one;
+    o = {};
+    int k = 0;
+    for (const Class &c : b->cls) {
+        if (!c.nact) continue;
+        if ((int64_t)c.nact * c.nlines > INT32_MAX || (int64_t)c.nact * std::max(c.ntiles_y, c.ntiles_z) > INT32_MAX)
+            return hipErrorInvalidValue;
+        const int total = c.nact * c.nlines;
+        const int L = c.x_lines ? c.x_lines : gpssc::x_lines_per_wave(c.chunk[0], total);
+        hx[k] = gpssc::XClassDesc{o.xblocks, c.nlines, total, c.chunk[0], L, c.d_active};
+        o.xblocks += (total + L - 1) / L;
+        o.cmax_x = std::max(o.cmax_x, c.chunk[0]);
+        o.lds_x = std::max(o.lds_x, L * (gpssc::kWave * c.chunk[0] + gpssc::kWave));
+        hy[k] = gpssc::YZClassDesc{o.yblocks, c.ntiles_y, c.ncol_y, c.xt_y, c.lanes[1], c.chunk[1], c.cols_y,
+                                   c.d_active};
+        o.yblocks += c.nact * c.ntiles_y;
+        o.cmax_y = std::max(o.cmax_y, c.chunk[1]);
+        o.thr_y = std::max(o.thr_y, c.xt_y * c.lanes[1]);
+        o.lds_y = std::max(o.lds_y, 2 * (size_t)c.xt_y * c.lanes[1] * yz_value_bytes(b->dtype, c.cols_y));
+        hz[k] = gpssc::YZClassDesc{o.zblocks, c.ntiles_z, c.ncol_z, c.xt_z, c.lanes[2], c.chunk[2], c.cols_z,
+                                   c.d_active};
+        o.zblocks += c.nact * c.ntiles_z;
+        o.cmax_z = std::max(o.cmax_z, c.chunk[2]);
+        o.thr_z = std::max(o.thr_z, c.xt_z * c.lanes[2]);
+        o.lds_z = std::max(o.lds_z, 2 * (size_t)c.xt_z * c.lanes[2] * yz_value_bytes(b->dtype, c.cols_z));
+        hn[k] = gpssc::NormClassDesc{o.nblocks, (int)(c.grid[0] * c.grid[1]), c.d_active};
+        o.nblocks += c.nact;
+        ++k;
+    }
+    o.ncls = k;
+    if (!k) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(b->d_xcls, hx, sizeof(*hx) * (size_t)k, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_ycls, hy, sizeof(*hy) * (size_t)k, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_zcls, hz, sizeof(*hz) * (size_t)k, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_ncls, hn, sizeof(*hn) * (size_t)k, hipMemcpyHostToDevice, b->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    return e;
+}
+
 // Uploads the active list of every class (pinned staging, stream-ordered on
 // the batch's own queue, then waits so the staging can be reused).
 hipError_t upload_active(gp_batch *b)
@@ -176,7 +257,9 @@ hipError_t upload_active(gp_batch *b)
         }
         off += (int)c.members.size();
     }
-    return hipStreamSynchronize(b->own);
+    hipError_t e = hipStreamSynchronize(b->own);
+    if (e == hipSuccess) e = upload_classes(b);
+    return e;
 }
 
 // One step of the active solves of one class, queued on `st`.
@@ -198,9 +281,32 @@ hipError_t enqueue_class(gp_batch *b, const Class &c, hipStream_t st)
                                              (int)(c.grid[0] * c.grid[1]), b->d_dv, b->d_scales, b->d_flags, st);
 }
 
+// GP_BATCH_ONE_LAUNCH: one step of every active solve in four launches
+// (three in real time) over all classes, queued on `st`.
+hipError_t enqueue_classes(gp_batch *b, hipStream_t st)
+{
+    const auto &o = b->one;
+    if (!o.ncls) return hipSuccess;
+    const gpssc::Prec prec = static_cast<gpssc::Prec>(b->dtype);
+    const bool real = b->mode == GP_MODE_REAL;
+    hipError_t e = gpssc::launch_nu_x_classes(prec, real, o.cmax_x, o.lds_x, o.xblocks, b->d_psis, b->d_xargs,
+                                              b->d_xcls, o.ncls, real ? nullptr : b->d_scales, st);
+    if (e == hipSuccess)
+        e = gpssc::launch_strided_classes(prec, real, o.cmax_y, o.thr_y, o.lds_y, o.yblocks, b->d_psis,
+                                          b->d_yargs, b->d_ycls, o.ncls, nullptr, nullptr, st);
+    if (e == hipSuccess)
+        e = gpssc::launch_strided_classes(prec, real, o.cmax_z, o.thr_z, o.lds_z, o.zblocks, b->d_psis,
+                                          b->d_zargs, b->d_zcls, o.ncls, real ? nullptr : b->d_partials,
+                                          b->d_part_off, st);
+    if (e != hipSuccess || real) return e;
+    return gpssc::launch_norm_finalize_classes(o.nblocks, b->d_ncls, o.ncls, b->d_partials, b->d_part_off,
+                                               b->d_dv, b->d_scales, b->d_flags, st);
+}
+
 // One step of every active solve, queued on the batch's own stream.
 hipError_t enqueue_step(gp_batch *b)
 {
+    if (b->flags & GP_BATCH_ONE_LAUNCH) return enqueue_classes(b, b->own);
     for (const Class &c : b->cls) {
         if (!c.nact) continue;
         hipError_t e = enqueue_class(b, c, b->own);
@@ -253,10 +359,11 @@ hipError_t build_graph(gp_batch *b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_ok = false;
-    hipError_t e = make_branches(b);
+    const bool one = (b->flags & GP_BATCH_ONE_LAUNCH) != 0;
+    hipError_t e = one ? hipSuccess : make_branches(b);
     if (e == hipSuccess) e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = enqueue_step_branches(b);
+    hipError_t le = one ? enqueue_classes(b, b->own) : enqueue_step_branches(b);
     e = hipStreamEndCapture(b->own, &b->graph);
     if (le != hipSuccess) return le;
     if (e != hipSuccess) return e;
@@ -407,7 +514,15 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     if (!valid_dtype(dtype)) return fail(GP_ERR_INVALID, "unknown dtype");
     if (real_storage(dtype) && mode != GP_MODE_IMAG)
         return fail(GP_ERR_INVALID, "real storage (GP_R64, GP_R32) holds imaginary-time states only");
-    if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE | GP_BATCH_FINISH_F64)) return fail(GP_ERR_INVALID, "unknown flags");
+    if (flags & ~(GP_BATCH_GRAPH | GP_BATCH_TUNE | GP_BATCH_FINISH_F64 | GP_BATCH_ONE_LAUNCH))
+        return fail(GP_ERR_INVALID, "unknown flags");
+    // The launch over every class is switched off: its first GPU test (the
+    // complex64 case of test_one_launch_matches_per_class_launches_bitwise)
+    // ended in a device fault whose cause is not found; a CPU emulation of
+    // its kernels under AddressSanitizer shows every access in bounds and
+    // its y/z results bitwise equal to the per-class launches.
+    if (flags & GP_BATCH_ONE_LAUNCH)
+        return fail(GP_ERR_UNSUPPORTED, "GP_BATCH_ONE_LAUNCH is switched off (an unexplained device fault in its test)");
     if ((flags & GP_BATCH_FINISH_F64) && (mode != GP_MODE_IMAG || (dtype != GP_C64 && dtype != GP_R32)))
         return fail(GP_ERR_INVALID, "GP_BATCH_FINISH_F64 is for imaginary-time batches in GP_C64 or GP_R32");
     for (int i = 0; i < nsolves; ++i) {
@@ -497,11 +612,23 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     GB_ALLOC(b->d_obs_partials, sizeof(double) * (size_t)obs);
     GB_ALLOC(b->d_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)nsolves);
     for (Class &c : b->cls) GB_ALLOC(c.d_active, sizeof(int) * c.members.size());
+    if (flags & GP_BATCH_ONE_LAUNCH) {
+        const size_t nc = b->cls.size();
+        GB_ALLOC(b->d_xcls, sizeof(gpssc::XClassDesc) * nc);
+        GB_ALLOC(b->d_ycls, sizeof(gpssc::YZClassDesc) * nc);
+        GB_ALLOC(b->d_zcls, sizeof(gpssc::YZClassDesc) * nc);
+        GB_ALLOC(b->d_ncls, sizeof(gpssc::NormClassDesc) * nc);
+    }
 #undef GB_ALLOC
     e = hipHostMalloc((void **)&b->h_sums, sizeof(double) * gpssc::OBS_NSUMS * (size_t)nsolves, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_flags, sizeof(int) * (size_t)nsolves, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_psis, sizeof(void *) * (size_t)nsolves, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_active, sizeof(int) * (size_t)nsolves, hipHostMallocDefault);
+    if (e == hipSuccess && (flags & GP_BATCH_ONE_LAUNCH))
+        e = hipHostMalloc((void **)&b->h_cls,
+                          b->cls.size() * (sizeof(gpssc::XClassDesc) + 2 * sizeof(gpssc::YZClassDesc) +
+                                           sizeof(gpssc::NormClassDesc)),
+                          hipHostMallocDefault);
     if (e != hipSuccess) {
         release(b);
         return fail_hip(e, "hipHostMalloc");
@@ -644,6 +771,7 @@ gp_status gp_batch_set_psi(gp_batch *b, void *const *psi, const int64_t *elems)
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_psis, b->h_psis, sizeof(void *) * (size_t)b->n, hipMemcpyHostToDevice, b->own);
     if (e == hipSuccess) e = hipStreamSynchronize(b->own);
+    if (e == hipSuccess && !b->graph_ok) e = upload_classes(b);   // the shapes may have changed
     if (e != hipSuccess) return fail_hip(e, "binding psi");
     return GP_OK;
 }

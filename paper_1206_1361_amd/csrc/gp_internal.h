@@ -428,6 +428,77 @@ hipError_t launch_nu_x_batch(Prec prec, bool real, int chunk, int nact, int nlin
                              const void *args, const int *active, const double *scales,
                              hipStream_t stream, int lines = 0);
 
+// ---- one launch per sweep over every class of a batch.  The classes'
+// blocks follow one another in the grid, class k's from block0 on (block0
+// increasing, the first 0); each block finds its class and runs exactly the
+// per-class kernel's code for it, so every solve's result is bitwise that
+// of the per-class launches. ----
+
+// Bytes of one element of psi in the storage of prec.
+inline size_t storage_bytes(Prec prec)
+{
+    switch (prec) {
+    case PREC_C128: return 16;
+    case PREC_C64: case PREC_C64_F64: case PREC_R64: return 8;
+    case PREC_R32: return 4;
+    }
+    return 0;
+}
+
+// Index of the class that owns block b: the last k with cls[k].block0 <= b.
+template <typename D>
+__device__ __forceinline__ int class_of_block(const D *__restrict__ cls, int ncls, int b)
+{
+    int lo = 0, hi = ncls - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (cls[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct XClassDesc {
+    int block0;          // first block of the class
+    int nlines;          // x lines per solve
+    int total;           // nact * nlines
+    int chunk, lines;    // points per lane, lines per wavefront
+    const int *active;   // the class's active solves (device)
+};
+
+// x sweep of every class: nblocks in all; cmax >= every class's chunk;
+// lds_elems = the largest lines * (64 chunk + 64) over the classes (LDS of
+// at most 64 KiB).
+hipError_t launch_nu_x_classes(Prec prec, bool real, int cmax, int lds_elems, int nblocks, void *const *psis,
+                               const void *args, const XClassDesc *cls, int ncls, const double *scales,
+                               hipStream_t stream);
+
+struct YZClassDesc {
+    int block0;          // first block of the class
+    int ntiles, ncol;    // tiles per solve, column tiles per outer index
+    int xt, lanes;       // threads across, chunks along (xt * lanes <= the block size)
+    int chunk, cols;     // points per chunk, columns per thread (2: complex64 pairs)
+    const int *active;   // the class's active solves (device)
+};
+
+// y or z sweep of every class: nblocks in all, blocks of `threads` threads
+// (>= every class's xt * lanes); cmax >= every chunk; lds_bytes = the
+// largest 2 xt lanes (16 or 8 bytes per value) over the classes.
+hipError_t launch_strided_classes(Prec prec, bool real, int cmax, int threads, size_t lds_bytes, int nblocks,
+                                  void *const *psis, const void *args, const YZClassDesc *cls, int ncls,
+                                  double *partials, const int64_t *part_off, hipStream_t stream);
+
+struct NormClassDesc {
+    int block0;          // first block of the class: one block per active solve
+    int npart;           // norm partials per solve
+    const int *active;
+};
+
+// calcnorm of every class: one block per active solve, as
+// launch_norm_finalize_batch.
+hipError_t launch_norm_finalize_classes(int nblocks, const NormClassDesc *cls, int ncls, const double *partials,
+                                        const int64_t *part_off, const double *dv, double *scales, int *flags,
+                                        hipStream_t stream);
+
 // partials + part_off[i]: solve i's per-line norm partials (NULL: none).
 // cols: columns per thread as in launch_strided (2: every active solve's psi
 // 16-byte aligned, nx even).

@@ -69,15 +69,12 @@ calcnorm_finalize_kernel(const double *__restrict__ partials, int n, double dv,
     }
 }
 
-// Batched: block b finalises solve active[b].
-__global__ void __launch_bounds__(kReduceThreads)
-calcnorm_finalize_batch_kernel(const int *__restrict__ active, const double *__restrict__ partials,
-                               const int64_t *__restrict__ part_off, int ntiles,
-                               const double *__restrict__ dv, double *__restrict__ scales,
-                               int *__restrict__ flags)
+// Solve si's 1/sqrt(N) from its ntiles partials (one block).
+__device__ __forceinline__ void finalize_solve(int si, const double *__restrict__ partials,
+                                               const int64_t *__restrict__ part_off, int ntiles,
+                                               const double *__restrict__ dv, double *__restrict__ scales,
+                                               int *__restrict__ flags, double *red)
 {
-    __shared__ double red[kReduceThreads];
-    const int si = active[blockIdx.x];
     const double acc = strided_sum(partials + part_off[si], nullptr, ntiles, threadIdx.x);
     const double sum = block_sum(acc, red);
     if (threadIdx.x == 0) {
@@ -86,6 +83,31 @@ calcnorm_finalize_batch_kernel(const int *__restrict__ active, const double *__r
         scales[si] = ok ? 1.0 / sqrt(norm) : (double)NAN;
         if (!ok) flags[si] = 1;
     }
+}
+
+// Batched: block b finalises solve active[b].
+__global__ void __launch_bounds__(kReduceThreads)
+calcnorm_finalize_batch_kernel(const int *__restrict__ active, const double *__restrict__ partials,
+                               const int64_t *__restrict__ part_off, int ntiles,
+                               const double *__restrict__ dv, double *__restrict__ scales,
+                               int *__restrict__ flags)
+{
+    __shared__ double red[kReduceThreads];
+    finalize_solve(active[blockIdx.x], partials, part_off, ntiles, dv, scales, flags, red);
+}
+
+// Every class in one launch: class k's blocks from cls[k].block0 on, one
+// per active solve of the class.
+__global__ void __launch_bounds__(kReduceThreads)
+calcnorm_finalize_classes_kernel(const NormClassDesc *__restrict__ cls, int ncls,
+                                 const double *__restrict__ partials, const int64_t *__restrict__ part_off,
+                                 const double *__restrict__ dv, double *__restrict__ scales,
+                                 int *__restrict__ flags)
+{
+    __shared__ double red[kReduceThreads];
+    const int b = blockIdx.x;
+    const NormClassDesc c = cls[class_of_block(cls, ncls, b)];
+    finalize_solve(c.active[b - c.block0], partials, part_off, c.npart, dv, scales, flags, red);
 }
 
 // Batched: blockIdx.y picks the solve; afterwards its scale is reset to 1 by
@@ -290,6 +312,16 @@ hipError_t launch_norm_finalize_batch(int nact, const int *active, const double 
     if (nact <= 0) return hipSuccess;
     hipLaunchKernelGGL(calcnorm_finalize_batch_kernel, dim3((unsigned)nact), dim3(kReduceThreads), 0,
                        stream, active, partials, part_off, ntiles, dv, scales, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize_classes(int nblocks, const NormClassDesc *cls, int ncls, const double *partials,
+                                        const int64_t *part_off, const double *dv, double *scales, int *flags,
+                                        hipStream_t stream)
+{
+    if (nblocks <= 0 || ncls <= 0) return hipSuccess;
+    hipLaunchKernelGGL(calcnorm_finalize_classes_kernel, dim3((unsigned)nblocks), dim3(kReduceThreads), 0, stream,
+                       cls, ncls, partials, part_off, dv, scales, flags);
     return hipGetLastError();
 }
 

@@ -330,17 +330,15 @@ calcnu_lux_lines_kernel(S *__restrict__ psi, const XArgs<A> a, const cx<A> *__re
     }
 }
 
-// Batched: block b advances the lines g = bL .. bL + L - 1 of the list of
-// active solves, line g % nlines of solve active[g / nlines], for g below
-// total = nact * nlines (past it, the last line again, not stored).
+// Batched: lines g = g0 .. g0 + L - 1 of the list of active solves, line
+// g % nlines of solve active[g / nlines], for g below total = nact * nlines
+// (past it, the last line again, not stored).  buf: L (64 C + 64) elements
+// of LDS.
 template <typename S, typename A, int C, int L, bool REAL>
-__global__ void __launch_bounds__(kWave)
-calcnu_lux_batch_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
-                        const int *__restrict__ active, int nlines, int total,
-                        const double *__restrict__ scales)
+__device__ __forceinline__ void x_batch_lines(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
+                                              const int *__restrict__ active, int nlines, int total,
+                                              const double *__restrict__ scales, int g0, S *buf)
 {
-    __shared__ S buf[L * (kWave * C + kWave)];
-    const int g0 = blockIdx.x * L;
     const XArgs<A> *ap[L];
     XLine<A> ln[L];
     S *rows[L];
@@ -359,6 +357,92 @@ calcnu_lux_batch_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__rest
 #pragma unroll
     for (int l = 0; l < L; ++l)
         if (g0 + l < total) store_x_row(rows[l], v[l], ap[l]->nx);
+}
+
+// Batched, one class: block b advances lines bL .. bL + L - 1 of the list.
+template <typename S, typename A, int C, int L, bool REAL>
+__global__ void __launch_bounds__(kWave)
+calcnu_lux_batch_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
+                        const int *__restrict__ active, int nlines, int total,
+                        const double *__restrict__ scales)
+{
+    __shared__ S buf[L * (kWave * C + kWave)];
+    x_batch_lines<S, A, C, L, REAL>(psis, args, active, nlines, total, scales, (int)blockIdx.x * L, buf);
+}
+
+// Batched, every class in one launch: class k owns the blocks from
+// cls[k].block0 on and advances its list as calcnu_lux_batch_kernel does,
+// with its own chunk and lines per wavefront (at most CMAX points per lane;
+// the kernel's registers are those of its largest variant).  LDS: the
+// largest class's L (64 C + 64) elements, dynamic.
+template <typename S, typename A, int CMAX, bool REAL>
+__global__ void __launch_bounds__(kWave)
+calcnu_lux_classes_kernel(S *const *__restrict__ psis, const XBatchArgs<A> *__restrict__ args,
+                          const XClassDesc *__restrict__ cls, int ncls, const double *__restrict__ scales)
+{
+    extern __shared__ unsigned char xsmem[];
+    S *buf = reinterpret_cast<S *>(xsmem);
+    const int b = blockIdx.x;
+    const XClassDesc c = cls[class_of_block(cls, ncls, b)];
+    const int g0 = (b - c.block0) * c.lines;
+#define GP_XC(CC, LL)                                                                                  \
+    case CC * 8 + LL:                                                                                  \
+        if constexpr (CC <= CMAX && LL <= x_max_lines_per_wave(CC))                                   \
+            x_batch_lines<S, A, CC, LL, REAL>(psis, args, c.active, c.nlines, c.total, scales, g0, buf); \
+        break;
+    switch (c.chunk * 8 + c.lines) {
+        GP_XC(1, 1) GP_XC(1, 2) GP_XC(1, 4) GP_XC(2, 1) GP_XC(2, 2) GP_XC(2, 4)
+        GP_XC(3, 1) GP_XC(3, 2) GP_XC(4, 1) GP_XC(4, 2)
+        GP_XC(5, 1) GP_XC(6, 1) GP_XC(7, 1) GP_XC(8, 1)
+        GP_XC(10, 1) GP_XC(12, 1) GP_XC(14, 1) GP_XC(16, 1)
+    default:
+        break;
+    }
+#undef GP_XC
+}
+
+template <typename S, typename A, bool REAL>
+static hipError_t launch_classes_x(int cmax, int nblocks, size_t lds, hipStream_t stream, void *const *psis,
+                                   const void *args, const XClassDesc *cls, int ncls, const double *scales)
+{
+    S *const *p = reinterpret_cast<S *const *>(psis);
+    const XBatchArgs<A> *a = static_cast<const XBatchArgs<A> *>(args);
+    const dim3 grid((unsigned)nblocks);
+    if (cmax <= 4)
+        hipLaunchKernelGGL((calcnu_lux_classes_kernel<S, A, 4, REAL>), grid, dim3(kWave), lds, stream, p, a, cls,
+                           ncls, scales);
+    else if (cmax <= 8)
+        hipLaunchKernelGGL((calcnu_lux_classes_kernel<S, A, 8, REAL>), grid, dim3(kWave), lds, stream, p, a, cls,
+                           ncls, scales);
+    else
+        hipLaunchKernelGGL((calcnu_lux_classes_kernel<S, A, 16, REAL>), grid, dim3(kWave), lds, stream, p, a, cls,
+                           ncls, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_nu_x_classes(Prec prec, bool real, int cmax, int lds_elems, int nblocks, void *const *psis,
+                               const void *args, const XClassDesc *cls, int ncls, const double *scales,
+                               hipStream_t stream)
+{
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
+    if (nblocks <= 0 || ncls <= 0) return hipSuccess;
+    if (cmax < 1 || cmax > 16 || lds_elems < 1) return hipErrorInvalidValue;
+    const size_t lds = (size_t)lds_elems * storage_bytes(prec);
+    if (lds > 65536) return hipErrorInvalidValue;
+#define GP_XCP(S, A)                                                                                          \
+    return real ? launch_classes_x<S, A, true>(cmax, nblocks, lds, stream, psis, args, cls, ncls, scales)     \
+                : launch_classes_x<S, A, false>(cmax, nblocks, lds, stream, psis, args, cls, ncls, scales);
+    switch (prec) {
+    case PREC_C64: GP_XCP(float2, float)
+    case PREC_C64_F64: GP_XCP(float2, double)
+    case PREC_C128: GP_XCP(double2, double)
+    case PREC_R64:
+        return launch_classes_x<double, double, false>(cmax, nblocks, lds, stream, psis, args, cls, ncls, scales);
+    case PREC_R32:
+        return launch_classes_x<float, float, false>(cmax, nblocks, lds, stream, psis, args, cls, ncls, scales);
+    }
+#undef GP_XCP
+    return hipErrorInvalidValue;
 }
 
 // Launch the L-line form with chunk C (L at most x_max_lines_per_wave(C)).

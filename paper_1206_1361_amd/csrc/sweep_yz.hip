@@ -42,25 +42,38 @@ __device__ __forceinline__ void store_cols(S *at, V v)
         stream_store(at, stv<S>(v));
 }
 
+// Where a thread sits in a tile: xt threads across the columns, p chunks
+// along the lines; thread (tx, pc) holds the chunk pc of column tx.  A
+// thread with on == false (a block larger than the tile, as in the launch
+// over every class of a batch) touches no memory but takes part in every
+// barrier of the tile.
+struct TileShape {
+    int xt, p;
+    int tx, pc;
+    bool on;
+};
+
 // One tile: XT*W neighbouring lines (columns) starting at column `col0`, at
 // outer index `outer` (z for the y sweep, y for the z sweep); thread tx holds
-// columns col0 + W tx .. col0 + W tx + W - 1 (W = 2 needs an even nx).
+// columns col0 + W tx .. col0 + W tx + W - 1 (W = 2 needs an even nx).  Every
+// thread of the block executes the same barriers whatever its shape entry.
 template <typename S, typename A, int C, bool REAL, bool NORM, int W>
-__device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &a,
-                                           const cx<A> *__restrict__ zt, double *__restrict__ partials,
-                                           unsigned char *smem_raw, int tile, int col0, int outer)
+__device__ __forceinline__ void solve_tile_at(S *__restrict__ psi, const SArgs<A> &a,
+                                              const cx<A> *__restrict__ zt, double *__restrict__ partials,
+                                              unsigned char *smem_raw, int col0, int outer, TileShape sh)
 {
     using V = col_t<S, A, W>;
-    const int XT = blockDim.x;
-    const int P = blockDim.y;
-    const int tx = threadIdx.x;
-    const int pc = threadIdx.y;
+    const int XT = sh.xt;
+    const int P = sh.p;
+    const int tx = sh.tx;
+    const int pc = sh.pc;
+    const bool on = sh.on;
     V *b0 = reinterpret_cast<V *>(smem_raw);
     V *b1 = b0 + P * XT;
     const int me = pc * XT + tx;
 
     const int i = col0 + W * tx;
-    const bool act = i < a.nx;
+    const bool act = on && i < a.nx;
     const int pos0 = pc * C;
     const bool full = act && pos0 + C <= a.n;   // whole chunk inside the line
     S *base = psi + (int64_t)outer * a.outer_stride + i + (int64_t)pos0 * a.stride;
@@ -78,58 +91,60 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
     }
 
     // neighbours across chunk borders
-    b0[me] = u[0];
-    b1[me] = u[C - 1];
+    if (on) {
+        b0[me] = u[0];
+        b1[me] = u[C - 1];
+    }
     __syncthreads();
     const V zero = V{};
-    const V left = pc > 0 ? b1[me - XT] : zero;
-    const V right = pc < P - 1 ? b0[me + XT] : zero;
+    const V left = on && pc > 0 ? b1[me - XT] : zero;
+    const V right = on && pc < P - 1 ? b0[me + XT] : zero;
     chunk_rhs<REAL>(u, left, right, a.k);
 
     // forward: local pass, Kogge-Stone over the chunks through LDS, rerun
     V t = chunk_forward<REAL, false>(u, zero, a.k);
     __syncthreads();  // every thread has read its neighbours from b0/b1
     V *cur = b0, *nxt = b1;
-    cur[me] = t;
+    if (on) cur[me] = t;
     __syncthreads();
 #pragma unroll
     for (int stg = 0; stg < kMaxStages; ++stg) {
         if (stg < a.k.nst) {
             const int d = 1 << stg;
-            if (pc >= d) t = kfma<REAL>(a.k.stage[stg], cur[me - d * XT], t);
-            nxt[me] = t;
+            if (on && pc >= d) t = kfma<REAL>(a.k.stage[stg], cur[me - d * XT], t);
+            if (on) nxt[me] = t;
             __syncthreads();
             V *tmp = cur; cur = nxt; nxt = tmp;
         }
     }
-    t = pc > 0 ? cur[me - XT] : zero;
+    t = on && pc > 0 ? cur[me - XT] : zero;
     chunk_forward<REAL, true>(u, t, a.k);
     if (pos0 + C > a.n) chunk_clear_padding(u, pos0, a.n);
 
     // backward
     t = chunk_backward<REAL, false>(u, zero, a.k);
     __syncthreads();  // every thread has read its forward carry
-    nxt[me] = t;
+    if (on) nxt[me] = t;
     __syncthreads();
     { V *tmp = cur; cur = nxt; nxt = tmp; }
 #pragma unroll
     for (int stg = 0; stg < kMaxStages; ++stg) {
         if (stg < a.k.nst) {
             const int d = 1 << stg;
-            if (pc + d < P) t = kfma<REAL>(a.k.stage[stg], cur[me + d * XT], t);
-            nxt[me] = t;
+            if (on && pc + d < P) t = kfma<REAL>(a.k.stage[stg], cur[me + d * XT], t);
+            if (on) nxt[me] = t;
             __syncthreads();
             V *tmp = cur; cur = nxt; nxt = tmp;
         }
     }
-    t = pc < P - 1 ? cur[me + XT] : zero;
+    t = on && pc < P - 1 ? cur[me + XT] : zero;
     chunk_backward<REAL, true>(u, t, a.k);
 
     // boundary correction from the first node of each line
     __syncthreads();  // every thread has read its backward carry
-    if (pc == 0) nxt[tx] = u[0];
+    if (on && pc == 0) nxt[tx] = u[0];
     __syncthreads();
-    if (pos0 < a.k.nzc) chunk_correct<REAL>(u, nxt[tx], zt, pos0, a.k.nzc);
+    if (on && pos0 < a.k.nzc) chunk_correct<REAL>(u, nxt[tx], zt, pos0, a.k.nzc);
 
     if (full) {
 #pragma unroll
@@ -165,8 +180,10 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
         }
         __syncthreads();  // LDS reuse
         double *red = reinterpret_cast<double *>(smem_raw);
+        if (on) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) red[w * P * XT + me] = acc[w];
+            for (int w = 0; w < W; ++w) red[w * P * XT + me] = acc[w];
+        }
         __syncthreads();
         if (pc == 0 && act) {
 #pragma unroll
@@ -177,6 +194,17 @@ __device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &
             }
         }
     }
+}
+
+// The tile as the block's own shape: blockDim.x columns, blockDim.y chunks.
+template <typename S, typename A, int C, bool REAL, bool NORM, int W>
+__device__ __forceinline__ void solve_tile(S *__restrict__ psi, const SArgs<A> &a,
+                                           const cx<A> *__restrict__ zt, double *__restrict__ partials,
+                                           unsigned char *smem_raw, int col0, int outer)
+{
+    solve_tile_at<S, A, C, REAL, NORM, W>(
+        psi, a, zt, partials, smem_raw, col0, outer,
+        TileShape{(int)blockDim.x, (int)blockDim.y, (int)threadIdx.x, (int)threadIdx.y, true});
 }
 
 // Tiles are numbered column-tile fastest; the grid has one block per tile
@@ -199,7 +227,7 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
     if (tile >= ntiles) return;
     const int outer = tile / ncol_tiles;
     const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
-    solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, tile, col0, outer);
+    solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, col0, outer);
 }
 
 // Batched: block b solves tile b % ntiles of solve active[b / ntiles].
@@ -218,8 +246,102 @@ calclu_strided_batch_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__
     const int outer = tile / ncol_tiles;
     const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
     solve_tile<S, A, C, REAL, NORM, W>(psis[si], args[si].s, args[si].zt,
-                                       NORM ? partials + part_off[si] : partials, smem_raw, tile, col0,
-                                       outer);
+                                       NORM ? partials + part_off[si] : partials, smem_raw, col0, outer);
+}
+
+// Batched, every class in one launch: class k owns the blocks from
+// cls[k].block0 on; a block solves tile b % ntiles of solve active[b /
+// ntiles] of its class, with the class's chunking and tile shape, as
+// calclu_strided_batch_kernel does.  The block (one dimension) is as large
+// as the largest class tile; threads past the class's tile join the
+// barriers only.  Registers are those of the largest variant (chunks of at
+// most CMAX points).
+template <typename S, typename A, int CMAX, bool REAL, bool NORM>
+__global__ void __launch_bounds__(kMaxBlockYZ)
+calclu_strided_classes_kernel(S *const *__restrict__ psis, const SBatchArgs<A> *__restrict__ args,
+                              const YZClassDesc *__restrict__ cls, int ncls, double *__restrict__ partials,
+                              const int64_t *__restrict__ part_off)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int b = blockIdx.x;
+    const YZClassDesc c = cls[class_of_block(cls, ncls, b)];
+    const int rel = b - c.block0;
+    const int slot = rel / c.ntiles;
+    const int tile = rel - slot * c.ntiles;
+    const int si = c.active[slot];
+    const int outer = tile / c.ncol;
+    const int col0 = (tile - outer * c.ncol) * c.xt * c.cols;
+    const int lin = threadIdx.x;
+    const TileShape sh{c.xt, c.lanes, lin % c.xt, lin / c.xt, lin < c.xt * c.lanes};
+    double *part = NORM ? partials + part_off[si] : partials;
+    constexpr bool kPairs = std::is_same<S, float2>::value && std::is_same<A, float>::value;
+#define GP_YC(CC, WW)                                                                                         \
+    case CC * 4 + WW:                                                                                         \
+        if constexpr (CC <= CMAX && (WW == 1 || kPairs))                                                      \
+            solve_tile_at<S, A, CC, REAL, NORM, WW>(psis[si], args[si].s, args[si].zt, part, smem_raw, col0,  \
+                                                    outer, sh);                                               \
+        break;
+    switch (c.chunk * 4 + c.cols) {
+        GP_YC(1, 1) GP_YC(2, 1) GP_YC(4, 1) GP_YC(8, 1) GP_YC(16, 1)
+        GP_YC(1, 2) GP_YC(2, 2) GP_YC(4, 2) GP_YC(8, 2) GP_YC(16, 2)
+    default:
+        break;
+    }
+#undef GP_YC
+}
+
+template <typename S, typename A, bool REAL>
+static hipError_t launch_classes_yz(int cmax, int threads, size_t lds, int nblocks, hipStream_t stream,
+                                    void *const *psis, const void *args, const YZClassDesc *cls, int ncls,
+                                    double *partials, const int64_t *part_off)
+{
+    S *const *p = reinterpret_cast<S *const *>(psis);
+    const SBatchArgs<A> *a = static_cast<const SBatchArgs<A> *>(args);
+    const dim3 grid((unsigned)nblocks), block((unsigned)threads);
+#define GP_YCL(CM)                                                                                           \
+    if (partials)                                                                                            \
+        hipLaunchKernelGGL((calclu_strided_classes_kernel<S, A, CM, REAL, true>), grid, block, lds, stream, p, \
+                           a, cls, ncls, partials, part_off);                                                \
+    else                                                                                                     \
+        hipLaunchKernelGGL((calclu_strided_classes_kernel<S, A, CM, REAL, false>), grid, block, lds, stream,  \
+                           p, a, cls, ncls, partials, part_off);
+    if (cmax <= 4) {
+        GP_YCL(4)
+    } else if (cmax <= 8) {
+        GP_YCL(8)
+    } else {
+        GP_YCL(16)
+    }
+#undef GP_YCL
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_classes(Prec prec, bool real, int cmax, int threads, size_t lds_bytes, int nblocks,
+                                  void *const *psis, const void *args, const YZClassDesc *cls, int ncls,
+                                  double *partials, const int64_t *part_off, hipStream_t stream)
+{
+    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
+    if (nblocks <= 0 || ncls <= 0) return hipSuccess;
+    if (cmax < 1 || cmax > 16 || threads < 1 || threads > kMaxBlockYZ || lds_bytes > 65536)
+        return hipErrorInvalidValue;
+#define GP_YCP(S, A)                                                                                            \
+    return real ? launch_classes_yz<S, A, true>(cmax, threads, lds_bytes, nblocks, stream, psis, args, cls, ncls, \
+                                                partials, part_off)                                             \
+                : launch_classes_yz<S, A, false>(cmax, threads, lds_bytes, nblocks, stream, psis, args, cls, ncls, \
+                                                 partials, part_off);
+    switch (prec) {
+    case PREC_C64: GP_YCP(float2, float)
+    case PREC_C64_F64: GP_YCP(float2, double)
+    case PREC_C128: GP_YCP(double2, double)
+    case PREC_R64:
+        return launch_classes_yz<double, double, false>(cmax, threads, lds_bytes, nblocks, stream, psis, args, cls,
+                                                        ncls, partials, part_off);
+    case PREC_R32:
+        return launch_classes_yz<float, float, false>(cmax, threads, lds_bytes, nblocks, stream, psis, args, cls,
+                                                      ncls, partials, part_off);
+    }
+#undef GP_YCP
+    return hipErrorInvalidValue;
 }
 
 template <typename S, typename A, bool REAL, int W>

@@ -257,3 +257,71 @@ def test_fp32_batch_with_fp64_finish_meets_the_fp32_bounds(dtype):
         print(f"solve {i} {sp['grid']}: {steps[i]} steps, mu {obs[i]['mu']:.9f} oracle {robs['mu']:.9f}")
         assert abs(obs[i]["mu"] - robs["mu"]) <= 1e-7 * abs(robs["mu"]), i
         assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref)), i
+
+
+def specs_wide(seed=5):
+    """Classes that differ in every launch parameter: x chunks of 1, 2, 3
+    and 5 points (so 4, 2 and 1 lines per wavefront), y/z chunks of 2 to 16
+    points over 8 to 48 chunks, and lines over 256 points (complex64
+    pairs)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(24, 20, 16), (96, 40, 300), (130, 66, 48), (300, 24, 20), (48, 130, 96), (24, 20, 16)]
+    return [dict(grid=shp, dx=0.25, dt=0.01, trap=tuple(rng.uniform(0.5, 3.0, 3)),
+                 g=float(np.exp(rng.uniform(0, np.log(500.0))))) for shp in shapes]
+
+
+def initial_any(sp, seed, dtype):
+    psi = inputs.smooth_random_state(sp["grid"], (sp["dx"],) * 3, sp["trap"], seed=seed)
+    if dtype == "r32":
+        return torch.from_numpy(np.ascontiguousarray(psi.real).astype(np.float32)).cuda()
+    return torch.from_numpy(psi).to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+
+
+@pytest.mark.skip(reason="GP_BATCH_ONE_LAUNCH is switched off: the complex64 case of its first GPU run ended in a device fault (SIGABRT in observables) whose cause is not found; a CPU emulation of its kernels under AddressSanitizer shows every access in bounds")
+@pytest.mark.parametrize("tune", [False, True])
+@pytest.mark.parametrize("dtype,mode", [("c128", "imag"), ("c128", "real"), ("c64", "imag"), ("c64", "real"),
+                                        ("r32", "imag")])
+def test_one_launch_matches_per_class_launches_bitwise(dtype, mode, tune):
+    """GP_BATCH_ONE_LAUNCH (each sweep one launch over every class) against
+    the per-class launches: bitwise the same states and observables, with
+    graph replay, after the active set changes, and eagerly."""
+    specs = specs_wide()
+    psi0 = [initial_any(sp, 30 + i, dtype) for i, sp in enumerate(specs)]
+    mask = [1, 0, 1, 1, 0, 1]
+    out = {}
+    for one in (False, True):
+        psis = [t.clone() for t in psi0]
+        with gp.Batch(specs, mode=mode, dtype=dtype, graph=True, tune=tune, one_launch=one) as b:
+            b.bind(psis)
+            b.step(3)
+            b.set_active(mask)
+            b.step(2)
+            b.set_active(None)
+            b.step(1)
+            obs = b.observables()
+        out[one] = (psis, obs)
+    for i in range(len(specs)):
+        assert torch.equal(out[False][0][i], out[True][0][i]), i
+        for k in ("mu", "energy", "norm", "rms_r"):
+            assert out[False][1][i][k] == out[True][1][i][k], (i, k)
+
+
+@pytest.mark.skip(reason="GP_BATCH_ONE_LAUNCH is switched off: the complex64 case of its first GPU run ended in a device fault (SIGABRT in observables) whose cause is not found; a CPU emulation of its kernels under AddressSanitizer shows every access in bounds")
+def test_one_launch_solve_imag_and_eager_steps():
+    """Solves dropping out of the one-launch batch as they converge, and the
+    eager (graph-less) path: the same steps and bits as the per-class
+    batch."""
+    specs = specs_mixed(3, n=6)
+    psi0 = [initial(sp, 50 + i, "c64") for i, sp in enumerate(specs)]
+    res = {}
+    for one in (False, True):
+        psis = [t.clone() for t in psi0]
+        with gp.Batch(specs, mode="imag", dtype="c64", graph=not one, one_launch=one) as b:
+            b.bind(psis)
+            obs, steps, conv = b.solve_imag(tol=1e-6, check_every=10, max_steps=400)
+        res[one] = (psis, [o["mu"] for o in obs], list(steps), list(conv))
+    assert res[False][2] == res[True][2]
+    assert res[False][3] == res[True][3]
+    assert res[False][1] == res[True][1]
+    for i in range(len(specs)):
+        assert torch.equal(res[False][0][i], res[True][0][i]), i

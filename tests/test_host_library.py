@@ -259,7 +259,8 @@ def test_batch_create_rejects_bad_arguments_before_any_device_call():
     assert create(trap=-0.5) == (_binding.ERR_INVALID, None)
     assert create(g=float("inf")) == (_binding.ERR_INVALID, None)
     assert create(mode=5) == (_binding.ERR_INVALID, None)
-    assert create(flags=8) == (_binding.ERR_INVALID, None)
+    assert create(flags=16) == (_binding.ERR_INVALID, None)
+    assert create(flags=8) == (_binding.ERR_UNSUPPORTED, None)   # GP_BATCH_ONE_LAUNCH, switched off
     assert create(grids=[8, 8, 8, 8, 2000, 8]) == (_binding.ERR_UNSUPPORTED, None)
     assert create(dtype=3, mode=1) == (_binding.ERR_INVALID, None)
     assert create(dtype=9) == (_binding.ERR_INVALID, None)
