@@ -49,16 +49,19 @@ def _compile(src: pathlib.Path) -> pathlib.Path:
     return obj
 
 
-PROBE_SRC = PKG / "probe" / "pattern_copy.hip"
+PROBES = ["pattern_copy", "grid_sync"]   # measurement tools in probe/, not part of the library
 PROBE_BIN = PKG / "probe" / "pattern_copy"
 
 
 def build_probe() -> pathlib.Path:
-    """The access-pattern probe (a measurement tool, not part of the library)."""
-    cmd = [HIPCC, *[f for f in COMMON if f != "-fPIC"], "-o", str(PROBE_BIN), str(PROBE_SRC)]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"building the probe failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    """The measurement probes: probe/<name>.hip -> probe/<name>."""
+    for name in PROBES:
+        src = PKG / "probe" / f"{name}.hip"
+        binary = PKG / "probe" / name
+        cmd = [HIPCC, *[f for f in COMMON if f != "-fPIC"], "-o", str(binary), str(src)]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"building the probe {name} failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     return PROBE_BIN
 
 
@@ -75,7 +78,7 @@ def build(verbose: bool = False) -> pathlib.Path:
     os.replace(tmp, LIBRARY)
     build_probe()
     if verbose:
-        print(f"built {LIBRARY} and {PROBE_BIN}", file=sys.stderr)
+        print(f"built {LIBRARY} and the probes " + ", ".join(PROBES), file=sys.stderr)
     return LIBRARY
 
 
