@@ -140,7 +140,8 @@ int main(int argc, char **argv)
         {1, 32, 16, 1, 0}, {1, 32, 24, 1, 0}, {1, 16, 16, 1, 16}, {1, 16, 16, 1, 64},
         {2, 8, 8, 0, 0},  {2, 16, 8, 0, 0},  {2, 16, 8, 1, 0}, {2, 16, 16, 0, 0}, {2, 32, 16, 0, 0},
         {2, 64, 24, 0, 0}, {2, 32, 24, 0, 0}, {2, 16, 8, 0, 16}, {2, 16, 8, 0, 64}, {2, 16, 8, 0, 512},
-        {2, 16, 8, 0, 4096},
+        {2, 16, 8, 0, 4096}, {2, 16, 6, 0, 0}, {2, 16, 12, 0, 0}, {2, 32, 12, 0, 0}, {1, 16, 12, 1, 0},
+        {1, 32, 12, 1, 0}, {1, 16, 6, 1, 0},
     };
     // the largest padded array any shape addresses
     long need = N;
@@ -170,6 +171,8 @@ int main(int argc, char **argv)
         auto run = [&] {
             switch (s.c) {
             case 4: hipLaunchKernelGGL(tile_pass<4>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
+            case 6: hipLaunchKernelGGL(tile_pass<6>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
+            case 12: hipLaunchKernelGGL(tile_pass<12>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
             case 8: hipLaunchKernelGGL(tile_pass<8>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
             case 16: hipLaunchKernelGGL(tile_pass<16>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
             case 24: hipLaunchKernelGGL(tile_pass<24>, grid, block, 0, nullptr, psi, nx, n, stride, outer_stride, ncol, ntiles, s.xcd, scale); break;
