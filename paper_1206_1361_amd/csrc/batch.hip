@@ -520,7 +520,7 @@ gp_status gp_batch_create(int nsolves, const int64_t *grids, const double *dx, c
     // complex64 case of test_one_launch_matches_per_class_launches_bitwise)
     // ended in a device fault whose cause is not found; a CPU emulation of
     // its kernels under AddressSanitizer shows every access in bounds and
-    // its y/z results bitwise equal to the per-class launches.
+    // its results bitwise equal to the per-class launches.
     if (flags & GP_BATCH_ONE_LAUNCH)
         return fail(GP_ERR_UNSUPPORTED, "GP_BATCH_ONE_LAUNCH is switched off (an unexplained device fault in its test)");
     if ((flags & GP_BATCH_FINISH_F64) && (mode != GP_MODE_IMAG || (dtype != GP_C64 && dtype != GP_R32)))
