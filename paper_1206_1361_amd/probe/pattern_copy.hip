@@ -9,7 +9,10 @@
 // elements) are timed beside it as the copy ceiling.  A shape may pad the
 // array: PAD extra elements after every plane (z lines) or every row (y
 // lines), so that the line stride is no longer a power of two; the bytes
-// counted stay those of the unpadded array.  Prints one line per shape:
+// counted stay those of the unpadded array.  An optional argument sets nx
+// (default 512): with 256 the 16-byte elements stand for pairs of complex64
+// columns, so the shapes are those of the complex64 sweeps of 512x512x384,
+// which hold two neighbouring columns per thread.  Prints one line per shape:
 // time per pass (HIP events, mean of 10 after 3 warm-up passes), GB/s of
 // one read and one write of the array, and the fraction of 8 TB/s.
 //
@@ -18,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -73,7 +77,11 @@ __global__ void __launch_bounds__(256) stream_pass(d2 *psi, long n, double scale
 int main(int argc, char **argv)
 {
     const double scale = argc > 99 ? 2.0 : 1.0;
-    const int nx = 512, ny = 512, nz = 384;
+    const int nx = argc > 1 ? std::atoi(argv[1]) : 512, ny = 512, nz = 384;
+    if (nx < 64 || nx > 4096 || nx % 64 != 0) {
+        std::printf("nx must be a multiple of 64 in 64..4096\n");
+        return 1;
+    }
     const long N = (long)nx * ny * nz;
     d2 *psi = nullptr;
     CHECK(hipMalloc(&psi, N * sizeof(d2)));
@@ -97,7 +105,11 @@ int main(int argc, char **argv)
         (void)hipEventElapsedTime(&ms, a, b);
         return ms / 10.0f;
     };
-    std::printf("512x512x384 complex128, one read + one write of %.3f GiB per pass\n", N * 16.0 / (1 << 30));
+    if (nx == 256)
+        std::printf("512x512x384 complex64 as 256x512x384 pairs of columns (16 bytes), one read + one write of %.3f GiB per pass\n",
+                    N * 16.0 / (1 << 30));
+    else
+        std::printf("%dx512x384 complex128, one read + one write of %.3f GiB per pass\n", nx, N * 16.0 / (1 << 30));
     report("stream, 1 element per thread", time_it([&] {
                hipLaunchKernelGGL(stream_pass<1>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, nullptr, psi, N, scale);
            }));
@@ -118,6 +130,11 @@ int main(int argc, char **argv)
                    hipLaunchKernelGGL(stream_pass<8>, dim3((unsigned)((N + 511) / 512)), dim3(64), lds, nullptr, psi, N, scale);
                }));
     }
+    // one-wavefront blocks taking 256 16-byte elements each, as the x sweep
+    // moves a 512-point complex64 line
+    report("stream, 64-thread blocks x 4 elements", time_it([&] {
+               hipLaunchKernelGGL(stream_pass<4>, dim3((unsigned)((N + 255) / 256)), dim3(64), 0, nullptr, psi, N, scale);
+           }));
     report("stream, 64-thread blocks x 1 element", time_it([&] {
                hipLaunchKernelGGL(stream_pass<1>, dim3((unsigned)((N + 63) / 64)), dim3(64), 0, nullptr, psi, N, scale);
            }));
