@@ -317,7 +317,9 @@ typedef struct gp_batch gp_batch;
 
 enum {
     GP_BATCH_GRAPH = 1,  /* capture one step of all classes in a HIP graph and replay it */
-    GP_BATCH_TUNE = 2,   /* time the y/z block widths per class at creation (scratch memory) */
+    GP_BATCH_TUNE = 2,   /* time per class at creation, on scratch memory: the y/z block widths,
+                            column pairs (complex64, even Nx) and x lines per wavefront; none of
+                            them changes a result */
     GP_BATCH_FINISH_F64 = 4, /* imaginary-time GP_C64 / GP_R32 batches: gp_batch_solve_imag finishes
                                 each solve in FP64 storage (see there) */
     GP_BATCH_ONE_LAUNCH = 8  /* each sweep of a step one launch over every class (blocks find their
