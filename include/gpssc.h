@@ -93,7 +93,7 @@ typedef struct {
 /* Kernel classes reported by gp_profile_read. */
 enum {
     GP_KERNEL_NU_X = 0,     /* calcnu + calclux (+ pending renormalisation) */
-    GP_KERNEL_Y = 1,        /* calcluy (with calcluz where one launch solves both) */
+    GP_KERNEL_Y = 1,        /* calcluy */
     GP_KERNEL_Z = 2,        /* calcluz (+ per-line norm partial sums in imaginary time) */
     GP_KERNEL_NORM = 3,     /* calcnorm: partial sums -> 1/sqrt(N) on the device */
     GP_KERNEL_SCALE = 4,    /* end-of-call psi <- psi / sqrt(N) */
@@ -174,14 +174,8 @@ gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const doubl
  *                    keeps the chunked scan.
  * GP_SWEEP_AUTO    : the library's choice per axis (the default); at present
  *                    the chunked scan, which measured at least as fast on
- *                    every grid tried.  On small 3D grids (y and z lines of
- *                    at most 64 points, at most 2^18 points) the chunked y
- *                    and z sweeps then run in one launch, each block owning
- *                    a few x columns of every (y, z) plane; the lines are
- *                    solved exactly as GP_SWEEP_CHUNKED solves them, so the
- *                    results are bitwise the same.
- * GP_SWEEP_CHUNKED keeps one launch per axis.  The chunked and streamed
- * strategies solve the same matrices; they agree to rounding, not bitwise. */
+ *                    every grid tried.
+ * Both solve the same matrices; results agree to rounding, not bitwise. */
 typedef enum { GP_SWEEP_AUTO = 0, GP_SWEEP_CHUNKED = 1, GP_SWEEP_STREAM = 2 } gp_sweep;
 
 /* Sets the y/z strategy of a plan's later steps (calcluy, calcluz).  The

@@ -373,17 +373,6 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int
                           void *psi, const void *args, const void *zt, double *partials, bool xcd_ranges,
                           hipStream_t stream);
 
-// calcluy then calcluz of a small grid in one launch: block b owns columns
-// [b xw, b xw + xw) of every (y, z) plane (threads: block size, a multiple
-// of 64 holding at least one tile of either axis).  Lines are solved as
-// launch_strided solves them with one column per thread (cy, cz: the axes'
-// chunks, each 1, 2, 4 or 8), so psi and the z partials (nx * ny_outer
-// doubles, as launch_strided writes them; NULL in real time) are bitwise the
-// same.  ny_outer = nz (outer index of the y lines), nz_outer = ny.
-hipError_t launch_yz_small(Prec prec, bool real, int cy, int cz, int xw, int threads, void *psi,
-                           const void *yargs, const void *zty, int ny_outer, const void *zargs, const void *ztz,
-                           int nz_outer, double *partials, hipStream_t stream);
-
 // calcluy / calcluz streamed along the lines (sweep_stream.hip): one lane per
 // column (cols = 1) or column pair (cols = 2: complex64 with FP32 arithmetic,
 // nx and both strides even, psi 16-byte aligned), blocks of blk points (8,

@@ -57,10 +57,6 @@ struct gp_plan {
     // y/z strategy: block length of the streaming sweep, or 0 for the
     // chunked scan; stream_ok: the longest admissible block (0: none)
     int blk_y = 0, blk_z = 0, blk_ok_y = 0, blk_ok_z = 0;
-    // small grids: y and z in one launch (launch_yz_small) when yzs is set;
-    // yzs_xw > 0 where the grid admits it (columns per block, block size)
-    int yzs_xw = 0, yzs_threads = 0, yzs_blocks = 0;
-    bool yzs = false;
 
     unsigned char *d_tables = nullptr;
     size_t tab_off[3];
@@ -288,14 +284,7 @@ void set_sweep(gp_plan *p, gp_sweep s)
         else
             *blk[a] = stream_by_default(ok[a], p->dtype) ? ok[a] : 0;
     }
-    p->yzs = s == GP_SWEEP_AUTO && p->yzs_xw > 0 && !p->blk_y && !p->blk_z;
 }
-
-// The fused small-grid y/z sweep: columns per block, and the largest grid.
-#ifndef GPSSC_YZ_SMALL_COLS
-#define GPSSC_YZ_SMALL_COLS 2
-#endif
-constexpr int64_t kYZSmallPoints = 1 << 18;
 
 // Blocks per sweep and the complex64 column pairs, from the grid, the dtype
 // and the chunking (p->ax, p->xt_y, p->xt_z set).  One block per line (x)
@@ -323,21 +312,6 @@ void set_launch_shapes(gp_plan *p)
     const bool f32 = arith_f32(p->dtype);
     p->blk_ok_y = p->ndim >= 2 ? stream_block_len(p->ax[1], f32) : 0;
     p->blk_ok_z = p->ndim >= 3 ? stream_block_len(p->ax[2], f32) : 0;
-    // Small grids (y and z lines of at most 64 points, at most 2^18 points):
-    // the y and z sweeps in one launch, where the two launches' fixed costs
-    // are most of their time.  Lines of at most 64 points have chunks of
-    // 1, 2, 4 or 8 points.
-    p->yzs_xw = p->yzs_threads = p->yzs_blocks = 0;
-    auto small_chunk = [](int c) { return c == 1 || c == 2 || c == 4 || c == 8; };
-    if (p->ndim == 3 && grid[1] <= 64 && grid[2] <= 64 && grid[0] * grid[1] * grid[2] <= kYZSmallPoints &&
-        small_chunk(p->ax[1].chunk) && small_chunk(p->ax[2].chunk)) {
-        const int xw = (int)std::min<int64_t>(GPSSC_YZ_SMALL_COLS, grid[0]);
-        const int64_t need = std::max(xw * p->ax[1].lanes * grid[2], xw * p->ax[2].lanes * grid[1]);
-        p->yzs_threads = (int)std::min<int64_t>((need + gpssc::kWave - 1) / gpssc::kWave * gpssc::kWave,
-                                                gpssc::kMaxBlockYZ);
-        p->yzs_xw = xw;
-        p->yzs_blocks = (int)((grid[0] + xw - 1) / xw);
-    }
     set_sweep(p, GP_SWEEP_AUTO);
 }
 
@@ -460,13 +434,7 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
                                       T + p->tab_off[0], scale, nd == 1 ? parts : nullptr, p->stream);
         });
         if (e != hipSuccess) break;
-        if (nd == 3 && p->yzs) {
-            e = timed(p, GP_KERNEL_Y, [&] {
-                return gpssc::launch_yz_small(prec, real, p->ax[1].chunk, p->ax[2].chunk, p->yzs_xw,
-                                              p->yzs_threads, psi, yargs, T + p->tab_off[1], (int)p->n[2], zargs,
-                                              T + p->tab_off[2], (int)p->n[1], parts, p->stream);
-            });
-        } else if (nd >= 2) {
+        if (nd >= 2) {
             e = timed(p, GP_KERNEL_Y, [&] {
                 if (p->blk_y)
                     return gpssc::launch_stream(prec, real, p->blk_y, spair ? 2 : 1, (int)p->n[2], psi, yargs,
@@ -476,15 +444,16 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
                                              nd == 2 ? parts : nullptr, true, p->stream);
             });
             if (e != hipSuccess) break;
-            if (nd == 3)
-                e = timed(p, GP_KERNEL_Z, [&] {
-                    if (p->blk_z)
-                        return gpssc::launch_stream(prec, real, p->blk_z, spair ? 2 : 1, (int)p->n[1], psi,
-                                                    zargs, T + p->tab_off[2], parts, p->stream);
-                    return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
-                                                 pair_z ? 2 : 1, (int)p->n[1], psi, zargs, T + p->tab_off[2],
-                                                 parts, false, p->stream);
-                });
+        }
+        if (nd == 3) {
+            e = timed(p, GP_KERNEL_Z, [&] {
+                if (p->blk_z)
+                    return gpssc::launch_stream(prec, real, p->blk_z, spair ? 2 : 1, (int)p->n[1], psi, zargs,
+                                                T + p->tab_off[2], parts, p->stream);
+                return gpssc::launch_strided(prec, real, p->ax[2].chunk, pair_z ? p->xt2_z : p->xt_z,
+                                             pair_z ? 2 : 1, (int)p->n[1], psi, zargs, T + p->tab_off[2], parts,
+                                             false, p->stream);
+            });
         }
         if (e != hipSuccess || real) continue;
         e = timed(p, GP_KERNEL_NORM, [&] {
@@ -723,7 +692,6 @@ gp_status gp_plan_create_radial(gp_geom geom, const int64_t grid[3], const doubl
     *out = nullptr;
     p->geom = geom;
     p->blk_ok_y = p->blk_ok_z = 0;   // the radial plans keep the chunked scan
-    p->yzs_xw = 0;                    // in its separate launches
     set_sweep(p, GP_SWEEP_AUTO);
     const int chunk = p->ax[0].chunk;
     const int npad = gpssc::kWave * chunk;
@@ -971,10 +939,7 @@ gp_status gp_plan_describe(const gp_plan *p, char *buf, size_t len)
     // y/z columns per block: with column pairs (16-byte aligned psi), 2 per
     // thread; otherwise one
     char cols[2][64];
-    for (int a = 0; a < 2 && p->yzs; ++a)
-        std::snprintf(cols[a], sizeof cols[a], "y and z in one launch, %d cols x %d blocks of %d", p->yzs_xw,
-                      p->yzs_blocks, p->yzs_threads);
-    for (int a = 0; a < 2 && !p->yzs; ++a) {
+    for (int a = 0; a < 2; ++a) {
         const int xt = a ? p->xt_z : p->xt_y, blocks = a ? p->z_blocks : p->y_blocks;
         const int blk = a ? p->blk_z : p->blk_y;
         if (blk)

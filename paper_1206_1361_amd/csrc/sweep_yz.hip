@@ -13,8 +13,6 @@
 // kernel: per-chunk recurrences with a zero carry, the carries between chunks
 // from a Kogge-Stone scan through LDS, a rerun from the true carry, and the
 // rank-one boundary term from the first node.
-#include <algorithm>
-
 #include "sweep_common.h"
 
 namespace gpssc {
@@ -230,56 +228,6 @@ calclu_strided_kernel(S *__restrict__ psi, const SArgs<A> a, const cx<A> *__rest
     const int outer = tile / ncol_tiles;
     const int col0 = (tile - outer * ncol_tiles) * (int)blockDim.x * W;
     solve_tile<S, A, C, REAL, NORM, W>(psi, a, zt, partials, smem_raw, col0, outer);
-}
-
-// Small grids: calcluy and calcluz in one launch.  The y and z solves of a
-// column (fixed x) involve no other column, so block b owns the columns
-// [b XW, b XW + XW) of every (y, z) plane: it solves all their y lines,
-// waits at a barrier (its own stores are then visible to its own loads) and
-// solves all their z lines.  Every line is solved by solve_tile_at exactly
-// as calclu_strided_kernel solves it (same chunking, scan, correction and
-// norm partial), so psi and the partials are bitwise those of the two
-// separate launches.  Within a phase the block runs blockDim.x / (XW P)
-// tiles side by side, each in its own LDS slice of slot_bytes, looping when
-// a phase has more tiles (outer indices) than that; a barrier after each
-// round keeps the next round's LDS writes behind this round's last reads.
-template <typename S, typename A, int CY, int CZ, bool REAL, bool NORM>
-__global__ void __launch_bounds__(kMaxBlockYZ)
-calclu_yz_small_kernel(S *__restrict__ psi, const SArgs<A> ay, const cx<A> *__restrict__ zty, int ny_outer,
-                       const SArgs<A> az, const cx<A> *__restrict__ ztz, int nz_outer,
-                       double *__restrict__ partials, int xw, int slot_bytes)
-{
-    extern __shared__ unsigned char smem_raw[];
-    const int col0 = (int)blockIdx.x * xw;
-    const int T = (int)blockDim.x;
-    const int lin = (int)threadIdx.x;
-    {
-        const int tt = xw * ay.lanes;
-        const int slots = T / tt;
-        const int slot = lin / tt, r = lin - slot * tt;
-        unsigned char *mine = smem_raw + (size_t)(slot < slots ? slot : 0) * slot_bytes;
-        for (int o0 = 0; o0 < ny_outer; o0 += slots) {
-            const int outer = o0 + slot;
-            const bool on = slot < slots && outer < ny_outer;
-            solve_tile_at<S, A, CY, REAL, false, 1>(psi, ay, zty, nullptr, mine, col0, on ? outer : 0,
-                                                    TileShape{xw, ay.lanes, r % xw, r / xw, on});
-            __syncthreads();   // the tile's last LDS reads are done before the next tile writes
-        }
-    }
-    // the y results are stored (the last round's barrier) before any z line is read
-    {
-        const int tt = xw * az.lanes;
-        const int slots = T / tt;
-        const int slot = lin / tt, r = lin - slot * tt;
-        unsigned char *mine = smem_raw + (size_t)(slot < slots ? slot : 0) * slot_bytes;
-        for (int o0 = 0; o0 < nz_outer; o0 += slots) {
-            const int outer = o0 + slot;
-            const bool on = slot < slots && outer < nz_outer;
-            solve_tile_at<S, A, CZ, REAL, NORM, 1>(psi, az, ztz, partials, mine, col0, on ? outer : 0,
-                                                   TileShape{xw, az.lanes, r % xw, r / xw, on});
-            __syncthreads();
-        }
-    }
 }
 
 // Batched: block b solves tile b % ntiles of solve active[b / ntiles].
@@ -539,69 +487,6 @@ hipError_t launch_strided(Prec prec, bool real, int chunk, int xt, int cols, int
                                              stream);
     }
 #undef GP_S_PREC
-    return hipErrorInvalidValue;
-}
-
-// calcluy + calcluz of a small grid in one launch (calclu_yz_small_kernel).
-template <typename S, typename A, bool REAL>
-static hipError_t launch_yz_small_t(int cy, int cz, int xw, int threads, void *psi, const void *yargs,
-                                    const void *zty, int ny_outer, const void *zargs, const void *ztz,
-                                    int nz_outer, double *partials, hipStream_t stream)
-{
-    const SArgs<A> &ay = *static_cast<const SArgs<A> *>(yargs);
-    const SArgs<A> &az = *static_cast<const SArgs<A> *>(zargs);
-    if (xw < 1 || threads < 1 || threads > kMaxBlockYZ || threads % kWave != 0) return hipErrorInvalidValue;
-    if (ay.nx != az.nx || xw * ay.lanes > threads || xw * az.lanes > threads) return hipErrorInvalidValue;
-    using V = value_t<S, A>;
-    size_t slot = 2 * (size_t)xw * (size_t)std::max(ay.lanes, az.lanes) * sizeof(V);
-    if (partials) slot = std::max(slot, (size_t)xw * az.lanes * sizeof(double));
-    const size_t nslots = (size_t)std::max(threads / (xw * ay.lanes), threads / (xw * az.lanes));
-    const size_t lds = nslots * slot;
-    if (lds > 65536) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((ay.nx + xw - 1) / xw)), block((unsigned)threads);
-    S *p = static_cast<S *>(psi);
-    const cx<A> *zy = static_cast<const cx<A> *>(zty);
-    const cx<A> *zz = static_cast<const cx<A> *>(ztz);
-#define GP_YZS(CY, CZ)                                                                                    \
-    if (cy == CY && cz == CZ) {                                                                           \
-        if (partials)                                                                                     \
-            hipLaunchKernelGGL((calclu_yz_small_kernel<S, A, CY, CZ, REAL, true>), grid, block, lds,      \
-                               stream, p, ay, zy, ny_outer, az, zz, nz_outer, partials, xw, (int)slot);   \
-        else                                                                                              \
-            hipLaunchKernelGGL((calclu_yz_small_kernel<S, A, CY, CZ, REAL, false>), grid, block, lds,     \
-                               stream, p, ay, zy, ny_outer, az, zz, nz_outer, partials, xw, (int)slot);   \
-        return hipGetLastError();                                                                         \
-    }
-    GP_YZS(1, 1) GP_YZS(1, 2) GP_YZS(1, 4) GP_YZS(1, 8)
-    GP_YZS(2, 1) GP_YZS(2, 2) GP_YZS(2, 4) GP_YZS(2, 8)
-    GP_YZS(4, 1) GP_YZS(4, 2) GP_YZS(4, 4) GP_YZS(4, 8)
-    GP_YZS(8, 1) GP_YZS(8, 2) GP_YZS(8, 4) GP_YZS(8, 8)
-#undef GP_YZS
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_yz_small(Prec prec, bool real, int cy, int cz, int xw, int threads, void *psi,
-                           const void *yargs, const void *zty, int ny_outer, const void *zargs, const void *ztz,
-                           int nz_outer, double *partials, hipStream_t stream)
-{
-    if (real && (prec == PREC_R64 || prec == PREC_R32)) return hipErrorInvalidValue;  // real storage is imaginary time only
-#define GP_YZS_PREC(S, A)                                                                                    \
-    return real ? launch_yz_small_t<S, A, true>(cy, cz, xw, threads, psi, yargs, zty, ny_outer, zargs, ztz,  \
-                                                nz_outer, partials, stream)                                  \
-                : launch_yz_small_t<S, A, false>(cy, cz, xw, threads, psi, yargs, zty, ny_outer, zargs, ztz, \
-                                                 nz_outer, partials, stream);
-    switch (prec) {
-    case PREC_C64: GP_YZS_PREC(float2, float)
-    case PREC_C64_F64: GP_YZS_PREC(float2, double)
-    case PREC_C128: GP_YZS_PREC(double2, double)
-    case PREC_R64:
-        return launch_yz_small_t<double, double, false>(cy, cz, xw, threads, psi, yargs, zty, ny_outer, zargs,
-                                                        ztz, nz_outer, partials, stream);
-    case PREC_R32:
-        return launch_yz_small_t<float, float, false>(cy, cz, xw, threads, psi, yargs, zty, ny_outer, zargs,
-                                                      ztz, nz_outer, partials, stream);
-    }
-#undef GP_YZS_PREC
     return hipErrorInvalidValue;
 }
 

@@ -1,10 +1,7 @@
 """Build and run one_launch_step.cpp: the batch kernels of the library on the
-CPU, per class and in one launch over every class, under AddressSanitizer;
-or, with --yz-small, yz_small.cpp: the fused small-grid y/z kernel against
-the separate y and z kernels.
+CPU, per class and in one launch over every class, under AddressSanitizer.
 
     python tests/cpu_emulation/run.py [--all] [--real] [--mask]
-    python tests/cpu_emulation/run.py --yz-small
 
 The kernel sources are taken from paper_1206_1361_amd/csrc with two textual
 changes (dynamic LDS becomes a per-block heap buffer, static LDS a static
@@ -32,7 +29,6 @@ def main() -> int:
     ap.add_argument("--all", action="store_true", help="every block (needed for the bitwise comparison)")
     ap.add_argument("--real", action="store_true", help="real time instead of imaginary time")
     ap.add_argument("--mask", action="store_true", help="the test's mask of active solves")
-    ap.add_argument("--yz-small", action="store_true", help="the fused small-grid y/z kernel instead")
     args = ap.parse_args()
     with tempfile.TemporaryDirectory() as tmp:
         tmp = pathlib.Path(tmp)
@@ -43,10 +39,9 @@ def main() -> int:
             src = re.sub(r"extern __shared__ unsigned char (\w+)\[\];", r"unsigned char *\1 = g_lds;", src)
             src = src.replace("__shared__", "static")
             (tmp / f"{name}.cpp").write_text(src)
-        prog = "yz_small" if args.yz_small else "one_launch_step"
-        exe = tmp / prog
+        exe = tmp / "one_launch_step"
         cmd = [CLANG, "-std=c++20", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", f"-I{tmp}",
-               f"-I{HERE}", f"-I{ROOT / 'include'}", str(HERE / f"{prog}.cpp"), "-o", str(exe), "-lpthread"]
+               f"-I{HERE}", f"-I{ROOT / 'include'}", str(HERE / "one_launch_step.cpp"), "-o", str(exe), "-lpthread"]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode:
             print(res.stderr[-4000:])
@@ -54,14 +49,12 @@ def main() -> int:
         env = dict(os.environ)
         if args.all:
             env["ALL"] = "1"
-        run = [str(exe)] if args.yz_small else [str(exe), "real" if args.real else "imag"] + (["mask"] if args.mask else [])
+        run = [str(exe), "real" if args.real else "imag"] + (["mask"] if args.mask else [])
         res = subprocess.run(run, env=env, text=True, capture_output=True)
         sys.stdout.write(res.stdout)
         sys.stderr.write(res.stderr[-4000:])
         if res.returncode or "ERROR: AddressSanitizer" in res.stderr:
             return 1
-        if args.yz_small:
-            return 0 if "cases differing: 0" in res.stdout else 1
         if args.all and "solves differing: 0, partials equal: 1" not in res.stdout:
             return 1
         return 0
