@@ -1,7 +1,12 @@
 """Build and run one_launch_step.cpp: the batch kernels of the library on the
-CPU, per class and in one launch over every class, under AddressSanitizer.
+CPU, per class and in one launch over every class, under AddressSanitizer;
+or, with --server, server_host.cpp: the request server's host code against
+the host-runtime stand-in of host/, its engine thread running rounds while
+the main thread submits and polls, under AddressSanitizer or (--tsan)
+ThreadSanitizer.
 
     python tests/cpu_emulation/run.py [--all] [--real] [--mask]
+    python tests/cpu_emulation/run.py --server [--tsan] [--iters N]
 
 The kernel sources are taken from paper_1206_1361_amd/csrc with two textual
 changes (dynamic LDS becomes a per-block heap buffer, static LDS a static
@@ -29,7 +34,12 @@ def main() -> int:
     ap.add_argument("--all", action="store_true", help="every block (needed for the bitwise comparison)")
     ap.add_argument("--real", action="store_true", help="real time instead of imaginary time")
     ap.add_argument("--mask", action="store_true", help="the test's mask of active solves")
+    ap.add_argument("--server", action="store_true", help="the server's host code instead")
+    ap.add_argument("--tsan", action="store_true", help="with --server: ThreadSanitizer")
+    ap.add_argument("--iters", type=int, default=20, help="with --server: rounds of the scenarios")
     args = ap.parse_args()
+    if args.server:
+        return run_server(args)
     with tempfile.TemporaryDirectory() as tmp:
         tmp = pathlib.Path(tmp)
         for h in CSRC.glob("*.h"):
@@ -56,6 +66,24 @@ def main() -> int:
         if res.returncode or "ERROR: AddressSanitizer" in res.stderr:
             return 1
         if args.all and "solves differing: 0, partials equal: 1" not in res.stdout:
+            return 1
+        return 0
+
+
+def run_server(args) -> int:
+    with tempfile.TemporaryDirectory() as tmp:
+        exe = pathlib.Path(tmp) / "server_host"
+        san = "-fsanitize=thread" if args.tsan else "-fsanitize=address"
+        cmd = [CLANG, "-std=c++20", "-O1", "-g", san, "-fno-omit-frame-pointer", f"-I{HERE / 'host'}",
+               f"-I{ROOT / 'include'}", f"-I{CSRC}", str(HERE / "server_host.cpp"), "-o", str(exe), "-lpthread"]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode:
+            print(res.stderr[-4000:])
+            return 1
+        res = subprocess.run([str(exe), str(args.iters)], text=True, capture_output=True)
+        sys.stdout.write(res.stdout)
+        sys.stderr.write(res.stderr[-4000:])
+        if res.returncode or "Sanitizer" in res.stderr or "scenarios failing 0" not in res.stdout:
             return 1
         return 0
 
