@@ -41,3 +41,14 @@ inline hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, c
 inline hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t) { for (auto &op : x->ops) op(); return hipSuccess; }
 inline hipError_t hipGraphExecDestroy(hipGraphExec_t x) { delete x; return hipSuccess; }
 inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
+// event timing (the batch tuner) and pointer attributes (device checks)
+inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new MockEvent; return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b)
+{ *ms = 0.001f * (float)((a->x * 7 + b->x * 13) % 17 + 1); return hipSuccess; }
+enum hipMemoryType { hipMemoryTypeHost = 1, hipMemoryTypeDevice = 2, hipMemoryTypeManaged = 4 };
+struct hipPointerAttribute_t { hipMemoryType type = hipMemoryTypeDevice; int device = 0; };
+inline hipError_t hipPointerGetAttributes(hipPointerAttribute_t *a, const void *) { *a = hipPointerAttribute_t{}; return hipSuccess; }
+// the typed forms of the runtime's allocation calls
+template <typename T> inline hipError_t hipMalloc(T **p, size_t n) { return hipMalloc(reinterpret_cast<void **>(p), n); }
+template <typename T> inline hipError_t hipHostMalloc(T **p, size_t n, unsigned f) { return hipHostMalloc(reinterpret_cast<void **>(p), n, f); }

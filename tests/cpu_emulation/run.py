@@ -3,10 +3,12 @@ CPU, per class and in one launch over every class, under AddressSanitizer;
 or, with --server, server_host.cpp: the request server's host code against
 the host-runtime stand-in of host/, its engine thread running rounds while
 the main thread submits and polls, under AddressSanitizer or (--tsan)
-ThreadSanitizer.
+ThreadSanitizer; or, with --batch, batch_host.cpp: the batch's host code
+against the same stand-in, under AddressSanitizer.
 
     python tests/cpu_emulation/run.py [--all] [--real] [--mask]
     python tests/cpu_emulation/run.py --server [--tsan] [--iters N]
+    python tests/cpu_emulation/run.py --batch [--iters N]
 
 The kernel sources are taken from paper_1206_1361_amd/csrc with two textual
 changes (dynamic LDS becomes a per-block heap buffer, static LDS a static
@@ -35,11 +37,12 @@ def main() -> int:
     ap.add_argument("--real", action="store_true", help="real time instead of imaginary time")
     ap.add_argument("--mask", action="store_true", help="the test's mask of active solves")
     ap.add_argument("--server", action="store_true", help="the server's host code instead")
+    ap.add_argument("--batch", action="store_true", help="the batch's host code instead")
     ap.add_argument("--tsan", action="store_true", help="with --server: ThreadSanitizer")
     ap.add_argument("--iters", type=int, default=20, help="with --server: rounds of the scenarios")
     args = ap.parse_args()
-    if args.server:
-        return run_server(args)
+    if args.server or args.batch:
+        return run_host(args)
     with tempfile.TemporaryDirectory() as tmp:
         tmp = pathlib.Path(tmp)
         for h in CSRC.glob("*.h"):
@@ -70,12 +73,13 @@ def main() -> int:
         return 0
 
 
-def run_server(args) -> int:
+def run_host(args) -> int:
+    prog = "server_host" if args.server else "batch_host"
     with tempfile.TemporaryDirectory() as tmp:
-        exe = pathlib.Path(tmp) / "server_host"
-        san = "-fsanitize=thread" if args.tsan else "-fsanitize=address"
+        exe = pathlib.Path(tmp) / prog
+        san = "-fsanitize=thread" if args.tsan and args.server else "-fsanitize=address"
         cmd = [CLANG, "-std=c++20", "-O1", "-g", san, "-fno-omit-frame-pointer", f"-I{HERE / 'host'}",
-               f"-I{ROOT / 'include'}", f"-I{CSRC}", str(HERE / "server_host.cpp"), "-o", str(exe), "-lpthread"]
+               f"-I{ROOT / 'include'}", f"-I{CSRC}", str(HERE / f"{prog}.cpp"), "-o", str(exe), "-lpthread"]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode:
             print(res.stderr[-4000:])
@@ -83,7 +87,8 @@ def run_server(args) -> int:
         res = subprocess.run([str(exe), str(args.iters)], text=True, capture_output=True)
         sys.stdout.write(res.stdout)
         sys.stderr.write(res.stderr[-4000:])
-        if res.returncode or "Sanitizer" in res.stderr or "scenarios failing 0" not in res.stdout:
+        good = "scenarios failing 0" if args.server else "cases failing 0"
+        if res.returncode or "Sanitizer" in res.stderr or good not in res.stdout:
             return 1
         return 0
 
