@@ -26,7 +26,9 @@ over a bounded sample of the same workload.  Further objects:
 `small`: the 32^3 imaginary-time workload's mu, E and rms sizes on the GPU
   and from the oracle, with the oracle's time to finish;
 `latency`: end-to-end time of that solve (upload to observables on the
-  host), p50/p99 over repeated solves;
+  host), p50/p99 over repeated solves after four untimed ones (a plan records
+  a repeated step call as a HIP graph once per psi buffer, and fresh tensors
+  from torch's caching allocator come back in two buffers by turns);
 `batch`: 256 uneven imaginary-time ground states (grids 48^3 to 160^3, dx
   0.2, dt 0.004, each stopped when mu moves by less than 1e-8 between checks
   10 steps apart) in several storage forms, against the same solves one by
@@ -317,14 +319,14 @@ def latency(gp, torch, repeats: int) -> dict:
     psi0 = inputs.initial_state(w)
     times = []
     with gp.Plan(w.grid, w.dx, w.dt, *w.omega, w.g, mode=w.mode, dtype="c128") as plan:
-        for r in range(repeats + 2):
+        for r in range(repeats + 4):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             psi = torch.from_numpy(psi0).cuda()
             plan.step(psi, w.steps)
             plan.observables(psi)
             t1 = time.perf_counter()
-            if r >= 2:
+            if r >= 4:
                 times.append((t1 - t0) * 1e3)
     return {"workload": w.name, "steps": w.steps, "dtype": "c128", "solves": len(times),
             "p50_ms": round(float(np.percentile(times, 50)), 3),

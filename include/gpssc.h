@@ -188,7 +188,8 @@ gp_status gp_plan_set_sweep(gp_plan *plan, gp_sweep strategy);
 gp_status gp_plan_destroy(gp_plan *plan);
 
 /* Changes g (a quench) for the steps queued after this call.  The tables do
- * not depend on g, so nothing is rebuilt. */
+ * not depend on g, so nothing is rebuilt (a recorded gp_step graph is
+ * dropped, after waiting for the plan's stream). */
 gp_status gp_set_g(gp_plan *plan, double g);
 
 /* Changes the trap frequencies (gamma, nu, lambda >= 0, finite) for the
@@ -217,7 +218,17 @@ gp_status gp_set_stream(gp_plan *plan, void *hip_stream);
  * calcnorm.  In imaginary time psi has norm 1 when the queued work ends; the
  * per-step renormalisation is carried by the next step's first pass and a
  * final scaling pass, which equals renormalising after every step up to
- * rounding.  nsteps == 0 queues nothing.  The plan allocates nothing here. */
+ * rounding.  nsteps == 0 queues nothing.  A call that repeats one of the
+ * plan's last four calls (same psi, same nsteps, no profiling) is recorded
+ * once into a HIP graph (the plan then creates a capture stream and the
+ * graph; at most four are kept, the least recently used dropped first) and
+ * later identical calls replay it: the same launches with the same
+ * arguments, so the same results, with less launch overhead.  gp_set_g,
+ * gp_set_trap and gp_plan_set_sweep drop the graphs, after waiting for the
+ * plan's stream.
+ * While the plan's stream is being captured by the caller, calls queue the
+ * launches themselves.  Apart from those graphs the plan allocates nothing
+ * here; gp_step_noalloc never records one. */
 gp_status gp_step(gp_plan *plan, void *psi_dev, int64_t psi_elems, int64_t nsteps);
 
 /* gp_step with a time-dependent nonlinearity and trap, for driven dynamics

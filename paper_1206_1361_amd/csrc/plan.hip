@@ -17,6 +17,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "gp_internal.h"
@@ -36,6 +37,20 @@ struct ProfRec {
 };
 
 }  // namespace
+
+// A gp_step call's key for replay, and one recorded call.
+struct StepKey {
+    const void *psi;
+    int64_t nsteps;
+    bool operator==(const StepKey &o) const { return psi == o.psi && nsteps == o.nsteps; }
+};
+struct StepGraph {
+    StepKey key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t used;   // call counter of its last launch
+};
+constexpr size_t kStepKeys = 4, kStepGraphs = 4;
 
 struct gp_plan {
     int ndim = 3;        // space variables: x (1), x and y (2), or all three
@@ -72,6 +87,17 @@ struct gp_plan {
 
     int64_t steps_done = 0;
     hipEvent_t ev_switch = nullptr;   // orders a new stream after the old one (gp_set_stream)
+    // gp_step replay: a call that repeats one of the last kStepKeys calls
+    // (same psi, same step count) has its launches captured once, on
+    // cap_stream, into a graph that later identical calls replay on the
+    // plan's stream (at most kStepGraphs graphs, the least recently used
+    // dropped first).  Any change of the launches' arguments (g, trap, sweep
+    // strategy) drops them all.
+    hipStream_t cap_stream = nullptr;
+    std::vector<StepGraph> graphs;
+    std::vector<StepKey> recent;      // the last calls' keys, oldest first
+    uint64_t calls = 0;
+    bool graph_off = false;           // a capture failed: launch eagerly from then on
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> pool;
@@ -176,6 +202,11 @@ void release(gp_plan *p)
     }
     for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
     if (p->ev_switch) (void)hipEventDestroy(p->ev_switch);
+    for (StepGraph &g : p->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->d_partials) (void)hipFree(p->d_partials);
     if (p->d_obs_partials) (void)hipFree(p->d_obs_partials);
@@ -351,8 +382,22 @@ gp_status read_flag(gp_plan *p)
     return GP_OK;
 }
 
+// Forgets the recorded calls (their launches hold the old arguments), after
+// waiting for the plan's stream, where a replay of them may still run.
+void drop_step_graph(gp_plan *p)
+{
+    if (!p->graphs.empty()) (void)hipStreamSynchronize(p->stream);
+    for (StepGraph &g : p->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+    p->recent.clear();
+}
+
 void set_g(gp_plan *p, double g)
 {
+    drop_step_graph(p);
     p->g = g;
     p->xd.g = g;
     p->xf.g = (float)g;
@@ -362,6 +407,7 @@ void set_g(gp_plan *p, double g)
 
 void set_trap(gp_plan *p, const double om_in[3])
 {
+    drop_step_graph(p);
     double om[3];
     if (p->geom) {   // radial axis: gamma; the axial trap's z (stored along y): lambda
         om[0] = om_in[0];
@@ -385,15 +431,9 @@ void set_trap(gp_plan *p, const double om_in[3])
     p->rf.x.hgz = p->xf.hgz;
 }
 
-// Queues nsteps steps.  With schedules, step s uses g_steps[s] and the trap
-// trap_steps[3s .. 3s+2]; the plan keeps the last step's values.
-gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, const double *g_steps,
-                    const double *trap_steps)
+// Queues the launches of nsteps steps on the plan's stream (psi checked).
+hipError_t enqueue_steps(gp_plan *p, void *psi, int64_t nsteps, const double *g_steps, const double *trap_steps)
 {
-    DeviceGuard guard(p->device);
-    gp_status st = check_psi(p, psi, psi_elems);
-    if (st != GP_OK) return st;
-    if (nsteps == 0) return GP_OK;
     const gpssc::Prec prec = static_cast<gpssc::Prec>(p->dtype);
     const bool a32 = arith_f32(p->dtype);   // FP32 arithmetic
     const bool real = p->mode == GP_MODE_REAL;
@@ -465,6 +505,96 @@ gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, co
         const int64_t elems = p->n[0] * p->n[1] * p->n[2];
         e = timed(p, GP_KERNEL_SCALE,
                   [&] { return gpssc::launch_scale(prec, psi, elems, p->d_scale, p->stream); });
+    }
+    return e;
+}
+
+// The launches of nsteps steps on psi captured on the plan's capture stream
+// into a new graph (nothing runs), which replaces the least recently used
+// one when kStepGraphs are kept; on failure nothing is kept.
+hipError_t capture_steps(gp_plan *p, void *psi, int64_t nsteps, StepGraph **out)
+{
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    const hipStream_t user = p->stream;
+    p->stream = p->cap_stream;   // the launchers queue on p->stream
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t le = enqueue_steps(p, psi, nsteps, nullptr, nullptr);
+        e = hipStreamEndCapture(p->cap_stream, &g);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    }
+    p->stream = user;
+    if (e != hipSuccess) {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (p->graphs.size() >= kStepGraphs) {   // the least recently used one goes
+        auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                    [](const StepGraph &a, const StepGraph &b) { return a.used < b.used; });
+        (void)hipStreamSynchronize(user);   // a replay of it may still run
+        (void)hipGraphExecDestroy(lru->exec);
+        (void)hipGraphDestroy(lru->graph);
+        p->graphs.erase(lru);
+    }
+    p->graphs.push_back(StepGraph{StepKey{psi, nsteps}, g, x, p->calls});
+    *out = &p->graphs.back();
+    return hipSuccess;
+}
+
+// Queues nsteps steps.  With schedules, step s uses g_steps[s] and the trap
+// trap_steps[3s .. 3s+2]; the plan keeps the last step's values.  A call
+// that repeats one of the last few (same psi and step count, no schedule,
+// no profiling) is captured once and replayed from then on: the same
+// launches with the same arguments, so the same results.
+gp_status run_steps(gp_plan *p, void *psi, int64_t psi_elems, int64_t nsteps, const double *g_steps,
+                    const double *trap_steps)
+{
+    DeviceGuard guard(p->device);
+    gp_status st = check_psi(p, psi, psi_elems);
+    if (st != GP_OK) return st;
+    if (nsteps == 0) return GP_OK;
+    // a caller capturing the plan's stream into a graph of its own gets the
+    // launches themselves
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    bool capturing = false;
+    if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        capturing = true;
+    } else {
+        capturing = cs != hipStreamCaptureStatusNone;
+    }
+    const bool plain = !g_steps && !trap_steps && !p->profiling && !p->graph_off && !capturing;
+    hipError_t e = hipSuccess;
+    const StepKey key{psi, nsteps};
+    ++p->calls;
+    StepGraph *hit = nullptr;
+    if (plain)
+        for (StepGraph &g : p->graphs)
+            if (g.key == key) hit = &g;
+    if (!hit && plain && std::find(p->recent.begin(), p->recent.end(), key) != p->recent.end()) {
+        e = capture_steps(p, psi, nsteps, &hit);
+        if (e != hipSuccess) {   // not capturable here: launch eagerly, now and later
+            (void)hipGetLastError();
+            p->graph_off = true;
+            hit = nullptr;
+        }
+    }
+    if (hit) {
+        hit->used = p->calls;
+        e = hipGraphLaunch(hit->exec, p->stream);
+    } else {
+        e = enqueue_steps(p, psi, nsteps, g_steps, trap_steps);
+    }
+    if (plain) {
+        p->recent.erase(std::remove(p->recent.begin(), p->recent.end(), key), p->recent.end());
+        p->recent.push_back(key);
+        if (p->recent.size() > kStepKeys) p->recent.erase(p->recent.begin());
     }
     if (e != hipSuccess) return fail_hip(e, "launching a step kernel");
     p->steps_done += nsteps;
@@ -756,6 +886,7 @@ gp_status gp_set_g(gp_plan *plan, double g)
 {
     if (!plan) return fail(GP_ERR_INVALID, "plan is NULL");
     if (!std::isfinite(g)) return fail(GP_ERR_INVALID, "g must be finite");
+    DeviceGuard guard(plan->device);
     set_g(plan, g);
     return GP_OK;
 }
@@ -784,6 +915,7 @@ gp_status gp_set_trap(gp_plan *plan, double gamma, double nu, double lambda)
     const double om[3] = {gamma, nu, lambda};
     for (double w : om)
         if (!std::isfinite(w) || w < 0.0) return fail(GP_ERR_INVALID, "trap frequencies must be finite and >= 0");
+    DeviceGuard guard(plan->device);
     set_trap(plan, om);
     return GP_OK;
 }
@@ -967,6 +1099,8 @@ gp_status gp_plan_set_sweep(gp_plan *p, gp_sweep strategy)
     if (!p) return fail(GP_ERR_INVALID, "plan is NULL");
     if (strategy != GP_SWEEP_AUTO && strategy != GP_SWEEP_CHUNKED && strategy != GP_SWEEP_STREAM)
         return fail(GP_ERR_INVALID, "unknown sweep strategy");
+    DeviceGuard guard(p->device);
+    drop_step_graph(p);
     set_sweep(p, strategy);
     return GP_OK;
 }
