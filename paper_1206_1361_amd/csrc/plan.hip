@@ -1272,6 +1272,7 @@ gp_status gp_step_noalloc(const int64_t grid[3], const double dx[3], double dt, 
     p.dtype = dtype;
     p.stream = static_cast<hipStream_t>(hip_stream);
     p.device = dev;
+    p.graph_off = true;   // no step replay: it would record call keys and graphs
     const bool real = mode == GP_MODE_REAL;
     const cplx *zt[3];
     size_t elem_off = 0;

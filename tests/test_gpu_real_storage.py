@@ -91,9 +91,9 @@ def test_real_storage_batch_matches_single_plans(dtype):
         assert obs[i]["mu"] == robs["mu"], i
 
 
-@pytest.mark.skip(reason="one run ended in a segmentation fault on a native (runtime) thread after the server "
-                         "had closed, the signature of the unexplained server abort; off the device until its "
-                         "cause is found")
+@pytest.mark.skip(reason="servers with real storage: unexplained crashes on a native thread in three runs "
+                         "(this test: a segmentation fault after its server had closed); off the device until "
+                         "the cause is found")
 def test_real_storage_server_matches_plan():
     rng = np.random.default_rng(12)
     with gp.Server(dtype="r64", hbm_budget=64 << 20, max_slots=8, check_every=10) as srv:
